@@ -1,0 +1,425 @@
+"""Pins of the FP64 oracle against things other than itself: hand-worked
+examples, brute-force loops, library routines (numpy, torch CPU float64),
+closed forms and invariants.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import ref
+from paper_2108_12430_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+
+
+def brute_conv1d(x, w, b, s, p):
+    B, ci, L = x.shape
+    co, _, k = w.shape
+    lout = (L + 2 * p - k) // s + 1
+    y = np.zeros((B, co, lout))
+    for bb in range(B):
+        for o in range(co):
+            for t in range(lout):
+                acc = b[o]
+                for i in range(ci):
+                    for j in range(k):
+                        q = s * t - p + j
+                        if 0 <= q < L:
+                            acc += w[o, i, j] * x[bb, i, q]
+                y[bb, o, t] = acc
+    return y
+
+
+def brute_convT(x, w, b, s, p, op):
+    B, ci, L = x.shape
+    _, co, k = w.shape
+    lout = (L - 1) * s - 2 * p + k + op
+    y = np.zeros((B, co, lout))
+    for bb in range(B):
+        for o in range(co):
+            y[bb, o, :] = b[o]
+            for i in range(ci):
+                for t in range(L):
+                    for j in range(k):
+                        u = s * t - p + j
+                        if 0 <= u < lout:
+                            y[bb, o, u] += w[i, o, j] * x[bb, i, t]
+    return y
+
+
+# ---------------------------------------------------------------- worked examples
+
+def test_golden_conv():
+    for key in ("conv1d_s1", "conv1d_s2"):
+        g = GOLD[key]
+        y = ref.conv1d(np.array(g["x"], float)[None, None], np.array(g["w"], float)[None, None],
+                       [g["b"]], g["stride"], g["pad"])
+        np.testing.assert_array_equal(y[0, 0], g["y"])
+    g = GOLD["convT_s2"]
+    y = ref.conv_transpose1d(np.array(g["x"], float)[None, None], np.array(g["w"], float)[None, None],
+                             [g["b"]], g["stride"], g["pad"], g["out_pad"])
+    np.testing.assert_array_equal(y[0, 0], g["y"])
+
+
+def test_golden_snapshot_and_causal():
+    g = GOLD["snapshot"]
+    st = np.zeros((1, g["W"]))
+    for upd, exp in zip(g["updates"], g["states"]):
+        st = ref.snapshot_update(st, np.array(upd, float)[None])
+        np.testing.assert_array_equal(st[0], exp)
+    g = GOLD["causal_clean"]
+    tail, clean = ref.causal_clean(np.array(g["noise"], float)[None], np.array(g["strain_new"], float)[None])
+    np.testing.assert_array_equal(tail[0], g["tail"])
+    np.testing.assert_array_equal(clean[0], g["clean"])
+    g = GOLD["bandwidth_reduction"]
+    assert g["fs"] // g["r"] == g["new_per_request"]
+    assert g["W"] // g["new_per_request"] == g["reduction"]
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("p", [0, 1, 3])
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_conv1d_bruteforce(s, p, k):
+    if p >= k:
+        pytest.skip("pad >= k not used")
+    rng = np.random.default_rng(10 * s + p + 100 * k)
+    x = rng.standard_normal((2, 3, 17))
+    w = rng.standard_normal((2, 3, k))
+    b = rng.standard_normal(2)
+    np.testing.assert_allclose(ref.conv1d(x, w, b, s, p), brute_conv1d(x, w, b, s, p), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("s,p,op", [(1, 0, 0), (1, 3, 0), (2, 3, 1), (2, 1, 0), (2, 0, 1)])
+def test_convT_bruteforce(s, p, op):
+    rng = np.random.default_rng(7 + s + p + op)
+    x = rng.standard_normal((2, 3, 11))
+    w = rng.standard_normal((3, 2, 7))
+    b = rng.standard_normal(2)
+    np.testing.assert_allclose(ref.conv_transpose1d(x, w, b, s, p, op), brute_convT(x, w, b, s, p, op),
+                               rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- library routines
+
+def test_conv_single_channel_is_correlate():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(40)
+    w = rng.standard_normal(7)
+    y = ref.conv1d(x[None, None], w[None, None], [0.0], 1, 3)[0, 0]
+    np.testing.assert_allclose(y, np.correlate(np.pad(x, 3), w, "valid"), atol=1e-12)
+
+
+def test_convT_single_channel_is_convolve():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(20)
+    w = rng.standard_normal(7)
+    # stride 1: full convolution cropped by the padding
+    y = ref.conv_transpose1d(x[None, None], w[None, None], [0.0], 1, 3, 0)[0, 0]
+    np.testing.assert_allclose(y, np.convolve(x, w, "full")[3:3 + 20], atol=1e-12)
+    # stride 2: zero-upsample then convolve, crop p, keep (L-1)2 - 2p + k + op samples
+    up = np.zeros(2 * 20 - 1)
+    up[::2] = x
+    full = np.concatenate([np.convolve(up, w, "full"), [0.0]])
+    y2 = ref.conv_transpose1d(x[None, None], w[None, None], [0.0], 2, 3, 1)[0, 0]
+    np.testing.assert_allclose(y2, full[3:3 + 40], atol=1e-12)
+
+
+@pytest.mark.parametrize("layer", synth.deepclean_layers())
+def test_layers_match_torch(layer):
+    typ, ci, co, k, s, p, op, _ = layer
+    rng = np.random.default_rng(ci * 100 + co)
+    L = 64 if typ == "conv" else 32
+    x = rng.standard_normal((2, ci, L))
+    b = rng.standard_normal(co)
+    if typ == "conv":
+        w = rng.standard_normal((co, ci, k))
+        y = ref.conv1d(x, w, b, s, p)
+        yt = F.conv1d(torch.from_numpy(x), torch.from_numpy(w), torch.from_numpy(b), stride=s, padding=p)
+    else:
+        w = rng.standard_normal((ci, co, k))
+        y = ref.conv_transpose1d(x, w, b, s, p, op)
+        yt = F.conv_transpose1d(torch.from_numpy(x), torch.from_numpy(w), torch.from_numpy(b), stride=s,
+                                padding=p, output_padding=op)
+    np.testing.assert_allclose(y, yt.numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_batchnorm_matches_torch():
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((4, 5, 33)) * 2 + 0.3
+    g, b, m, v = rng.uniform(0.5, 1.5, 5), rng.normal(0, 0.1, 5), rng.normal(0, 0.1, 5), rng.uniform(0.5, 1.5, 5)
+    T = torch.from_numpy
+    np.testing.assert_allclose(ref.batchnorm_infer(y, g, b, m, v),
+                               F.batch_norm(T(y), T(m), T(v), T(g), T(b), False, 0.0, 1e-5).numpy(), atol=1e-12)
+    out, mean, var = ref.batchnorm_train(y, g, b)
+    np.testing.assert_allclose(out, F.batch_norm(T(y), None, None, T(g), T(b), True, 0.0, 1e-5).numpy(), atol=1e-12)
+    np.testing.assert_allclose(var, y.var(axis=(0, 2)), atol=1e-12)
+
+
+def test_bn_fold_identity():
+    """BN(conv(x)) equals a conv with folded weights w*scale and bias
+    (b - mean)*scale + beta."""
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, 3, 30))
+    w, b = rng.standard_normal((4, 3, 7)), rng.standard_normal(4)
+    g, be, m, v = rng.uniform(0.5, 1.5, 4), rng.normal(0, .1, 4), rng.normal(0, .1, 4), rng.uniform(.5, 1.5, 4)
+    sc = g / np.sqrt(v + 1e-5)
+    lhs = ref.batchnorm_infer(ref.conv1d(x, w, b, 2, 3), g, be, m, v)
+    rhs = ref.conv1d(x, w * sc[:, None, None], (b - m) * sc + be, 2, 3)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-12)
+
+
+def _torch_deepclean(params, layers, train):
+    ps = ref.unpack_deepclean(params, layers)
+    mods = []
+    for (typ, ci, co, k, s, p, op, bn), d in zip(layers, ps):
+        if typ == "conv":
+            m = torch.nn.Conv1d(ci, co, k, stride=s, padding=p).double()
+        else:
+            m = torch.nn.ConvTranspose1d(ci, co, k, stride=s, padding=p, output_padding=op).double()
+        with torch.no_grad():
+            m.weight.copy_(torch.from_numpy(d["w"]))
+            m.bias.copy_(torch.from_numpy(d["b"]))
+        mods.append(m)
+        if bn:
+            n = torch.nn.BatchNorm1d(co, eps=1e-5, momentum=0.0).double()
+            with torch.no_grad():
+                n.weight.copy_(torch.from_numpy(d["gamma"]))
+                n.bias.copy_(torch.from_numpy(d["beta"]))
+                n.running_mean.copy_(torch.from_numpy(d["mean"]))
+                n.running_var.copy_(torch.from_numpy(d["var"]))
+            mods += [n, torch.nn.Tanh()]
+    net = torch.nn.Sequential(*mods)
+    net.train(train)
+    return net
+
+
+@pytest.mark.parametrize("train", [False, True])
+def test_deepclean_matches_torch(train):
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    x, _ = synth.witness_stream(1, 4096)
+    xb = np.stack([x, x[:, ::-1].copy()])
+    y = ref.deepclean_forward(params, xb, layers, train=train)
+    yt = _torch_deepclean(params, layers, train)(torch.from_numpy(xb.astype(np.float64)))
+    np.testing.assert_allclose(y, yt.detach().numpy()[:, 0], rtol=1e-10, atol=1e-12)
+
+
+def test_bbhnet_matches_torch():
+    params = synth.bbhnet_params(0)
+    x, _ = synth.bbh_windows(3, 4)
+    ps, head = ref.unpack_bbhnet(params)
+    a = torch.from_numpy(x.astype(np.float64))
+    T = torch.from_numpy
+    for d in ps:
+        h = F.relu(F.conv1d(a, T(d["wa"]), T(d["ba"]), stride=2, padding=3))
+        h = F.conv1d(h, T(d["wb"]), T(d["bb"]), stride=1, padding=3)
+        a = F.relu(h + F.conv1d(a, T(d["ws"]), T(d["bs"]), stride=2))
+    logit = a.mean(dim=2) @ T(head["w"][0]) + head["b"][0]
+    np.testing.assert_allclose(ref.bbhnet_forward(params, x), logit.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_deepclean_grad_matches_torch_autograd():
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    x, strain = synth.witness_stream(4, 2 * 2048)
+    xb = np.stack([x[:, :2048], x[:, 2048:]])
+    sb = np.stack([strain[:2048], strain[2048:]])
+    noise = ref.deepclean_forward(params, xb, layers, train=True)
+    loss, dn = ref.bandpass_mse(sb, noise, 4096.0, 55.0, 65.0)
+    g = ref.deepclean_grad(params, xb, dn, layers)
+    net = _torch_deepclean(params, layers, True)
+    out = net(torch.from_numpy(xb.astype(np.float64)))[:, 0]
+    out.backward(torch.from_numpy(dn))
+    tg = []
+    for m in net:
+        if isinstance(m, (torch.nn.Conv1d, torch.nn.ConvTranspose1d)):
+            tg += [m.weight.grad.numpy().ravel(), m.bias.grad.numpy()]
+        elif isinstance(m, torch.nn.BatchNorm1d):
+            tg += [m.weight.grad.numpy(), m.bias.grad.numpy(), np.zeros(m.num_features), np.zeros(m.num_features)]
+    tg = np.concatenate(tg)
+    assert np.max(np.abs(g - tg)) <= 1e-9 * np.max(np.abs(tg))
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_impulse_response():
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((2, 3, 7))
+    x = np.zeros((1, 3, 40))
+    t0 = 17
+    x[0, 1, t0] = 1.0
+    y = ref.conv1d(x, w, np.zeros(2), 2, 3)
+    for t in range(y.shape[2]):
+        j = t0 - 2 * t + 3
+        exp = w[:, 1, j] if 0 <= j < 7 else np.zeros(2)
+        np.testing.assert_array_equal(y[0, :, t], exp)
+    wt = rng.standard_normal((3, 2, 7))
+    x2 = np.zeros((1, 3, 20))
+    x2[0, 2, 5] = 1.0
+    y2 = ref.conv_transpose1d(x2, wt, np.zeros(2), 2, 3, 1)
+    exp = np.zeros((2, 40))
+    exp[:, 2 * 5 - 3: 2 * 5 - 3 + 7] = wt[2]
+    np.testing.assert_array_equal(y2[0], exp)
+
+
+def test_linearity_and_adjoint():
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((4, 3, 7))
+    x, y = rng.standard_normal((2, 3, 64)), rng.standard_normal((2, 3, 64))
+    f = lambda v: ref.conv1d(v, w, None, 2, 3)
+    np.testing.assert_allclose(f(2.5 * x - 0.5 * y), 2.5 * f(x) - 0.5 * f(y), atol=1e-12)
+    # <conv(x), z> == <x, convT(z)> (the dgrad relation)
+    z = rng.standard_normal((2, 4, 32))
+    lhs = np.sum(f(x) * z)
+    rhs = np.sum(x * ref.conv_transpose1d(z, w, None, 2, 3, 1))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+
+
+def test_shift_equivariance():
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal((2, 3, 7))
+    x = rng.standard_normal((1, 3, 80))
+    y = ref.conv1d(x, w, None, 2, 3)
+    ys = ref.conv1d(np.roll(x, 4, axis=2), w, None, 2, 3)
+    np.testing.assert_allclose(ys[..., 6:-4], y[..., 4:-6], atol=1e-12)
+
+
+def test_deepclean_zero_and_receptive_field():
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0).astype(np.float64)
+    ps = ref.unpack_deepclean(params, layers)
+    # zero biases, beta and mean give exactly zero output for zero input
+    p0 = params.copy()
+    off = 0
+    for (typ, ci, co, k, s, p, op, bn), d in zip(layers, ps):
+        off += ci * co * k
+        p0[off: off + co] = 0
+        off += co
+        if bn:
+            p0[off + co: off + 3 * co] = 0  # beta, mean
+            off += 4 * co
+    assert np.all(ref.deepclean_forward(p0, np.zeros((1, 21, 512)), layers) == 0)
+    x = synth.gaussian(9, (1, 21, 1024)).astype(np.float64)
+    y0 = ref.deepclean_forward(params, x, layers)
+    x2 = x.copy()
+    x2[0, 5, 500] += 1.0
+    d = np.nonzero(ref.deepclean_forward(params, x2, layers)[0] != y0[0])[0]
+    assert d.min() >= 500 - 93 and d.max() <= 500 + 93
+    assert d.min() < 500 - 60 and d.max() > 500 + 60
+
+
+def test_bbhnet_zero_convb_is_relu_shortcut():
+    params = synth.bbhnet_params(0).astype(np.float64)
+    ps, head = ref.unpack_bbhnet(params)
+    x, _ = synth.bbh_windows(11, 2, n=64)
+    # zero conv_b weights and bias of stage 1: stage output is relu(shortcut)
+    p = params.copy()
+    off = 32 * 2 * 7 + 32
+    p[off: off + 32 * 32 * 7 + 32] = 0
+    ps2, _ = ref.unpack_bbhnet(p)
+    d = ps2[0]
+    exp = np.maximum(ref.conv1d(x.astype(np.float64), d["ws"], d["bs"], 2, 0), 0)
+    a = np.maximum(ref.conv1d(x, d["wa"], d["ba"], 2, 3), 0)
+    h = ref.conv1d(a, d["wb"], d["bb"], 1, 3)
+    np.testing.assert_array_equal(h, 0 * h)
+    np.testing.assert_allclose(np.maximum(h + ref.conv1d(x, d["ws"], d["bs"], 2, 0), 0), exp)
+    # GAP + linear closed form: constant last-stage activation c gives w.sum()*c + b
+    g = np.full(128, 0.25)
+    assert abs(g @ head["w"][0] + head["b"][0] - (0.25 * head["w"].sum() + head["b"][0])) < 1e-12
+
+
+def test_snapshot_closed_form_random_strides():
+    rng = np.random.default_rng(12)
+    W, C = 96, 3
+    stream = rng.standard_normal((C, 2000))
+    st = np.zeros((C, W))
+    pos = 0
+    while pos < 1900:
+        s = int(rng.integers(1, W + 1))
+        st = ref.snapshot_update(st, stream[:, pos: pos + s])
+        pos += s
+        np.testing.assert_array_equal(st, ref.snapshot_after(stream, pos, W))
+
+
+# ---------------------------------------------------------------- band-pass loss
+
+def test_bandpass_projection_properties():
+    W, fs = 4096, 4096.0
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal((2, W))
+    pr = ref.bandpass(r, fs, 55, 65)
+    np.testing.assert_allclose(ref.bandpass(pr, fs, 55, 65), pr, atol=1e-12)      # P^2 = P
+    q = rng.standard_normal((2, W))
+    assert abs(np.sum(pr * q) - np.sum(r * ref.bandpass(q, fs, 55, 65))) < 1e-9   # P^T = P
+    # Parseval: time-domain energy equals the band's share of the spectrum
+    R = np.fft.rfft(r, axis=-1)
+    kk = ref.band_bins(W, fs, 55, 65)
+    assert kk.min() == 55 and kk.max() == 65
+    e_f = 2.0 * np.sum(np.abs(R[:, kk]) ** 2) / W
+    assert abs(np.sum(pr * pr) - e_f) < 1e-9 * e_f
+    t = np.arange(W) / fs
+    s60 = np.sin(2 * np.pi * 60 * t + 0.3)
+    np.testing.assert_allclose(ref.bandpass(s60[None], fs, 55, 65)[0], s60, atol=1e-10)
+    for f0 in (50.0, 70.0):
+        assert np.max(np.abs(ref.bandpass(np.sin(2 * np.pi * f0 * t)[None], fs, 55, 65))) < 1e-10
+    assert list(ref.band_bins(32768, 4096.0, 55, 65)[[0, -1]]) == [440, 520]
+
+
+def _fd_check(params, x, strain, layers, lossfn, eps=1e-3):
+    noise = ref.deepclean_forward(params, x, layers, train=True)
+    _, dn = lossfn(strain, noise)
+    g = ref.deepclean_grad(params, x, dn, layers)
+    fd = np.zeros_like(g)
+    for i in range(params.size):
+        pp, pm = params.copy(), params.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        lp = lossfn(strain, ref.deepclean_forward(pp, x, layers, train=True))[0]
+        lm = lossfn(strain, ref.deepclean_forward(pm, x, layers, train=True))[0]
+        fd[i] = (lp - lm) / (2 * eps)
+    return g, fd
+
+
+@pytest.mark.parametrize("loss", ["bandpass", "mse"])
+def test_grad_central_fd_tiny(loss):
+    layers = synth.tiny_layers()
+    params = synth.deepclean_params(5, layers).astype(np.float64)
+    x = synth.gaussian(5, (2, 4, 256)).astype(np.float64)
+    strain = synth.gaussian(6, (2, 256)).astype(np.float64)
+    if loss == "bandpass":
+        # add in-band content so the band-passed loss is not tiny
+        t = np.arange(256) / 4096.0
+        strain = strain + 3 * np.sin(2 * np.pi * 64 * t)
+        fn = lambda s, n: ref.bandpass_mse(s, n, 4096.0, 55.0, 65.0)
+    else:
+        fn = ref.mse
+    g, fd = _fd_check(params, x, strain, layers, fn, 1e-3)
+    # central differences carry an O(eps^2) truncation error: at eps = 1e-3 it
+    # measures a few 1e-6 of the largest gradient, and it shrinks 4x per halving
+    err = np.max(np.abs(g - fd)) / np.max(np.abs(fd))
+    assert err <= 2e-5, err
+    # Richardson extrapolation of eps and eps/2 cancels the eps^2 term
+    _, fd2 = _fd_check(params, x, strain, layers, fn, 5e-4)
+    rich = (4 * fd2 - fd) / 3
+    err_r = np.max(np.abs(g - rich)) / np.max(np.abs(rich))
+    assert err_r <= 1e-8, err_r
+    if loss == "mse":
+        # every trainable parameter gets a nonzero gradient under the plain MSE
+        nz = np.abs(g) > 0
+        # running mean/var entries (2*4) stay zero
+        assert nz.sum() == g.size - 8
+
+
+def test_shape_tables_agree():
+    """The generator's parameter layout and the oracle's layer table describe
+    the same networks (sizes from the workload: 39,312 conv weights, 185
+    biases, 184 normalised channels)."""
+    assert tuple(synth.deepclean_layers()) == tuple(ref.DEEPCLEAN_LAYERS)
+    assert tuple(synth.bbhnet_stages()) == tuple(ref.BBHNET_STAGES)
+    assert synth.deepclean_params(0).size == ref.n_params() == 39312 + 185 + 4 * 184
+    ref.unpack_bbhnet(synth.bbhnet_params(0))
