@@ -1,0 +1,250 @@
+/*
+ * gwstream.h - C ABI of libgwstream.so: streaming 1-D CNN inference and
+ * training kernels for gravitational-wave time series on MI355X (gfx950).
+ *
+ * The calls follow the paper's framing of online inference (Gunny et al.,
+ * "Hardware-accelerated Inference for Real-Time Gravitational-Wave
+ * Astronomy"):
+ *   - a stateful "snapshotter" holds each stream's previous input snapshot on
+ *     the device; a request carries floor(f_s/r) strictly new samples that
+ *     update it to the next snapshot (App. B.1)            -> snapshot_update
+ *   - the updated snapshot feeds the static models: a DeepClean-shaped 1-D
+ *     convolutional autoencoder that predicts witness-coupled noise (main
+ *     text, DeepClean paragraph)                           -> deepclean_forward
+ *     and a BBHnet-shaped 1-D CNN that scores binary-black-hole likelihood
+ *     (main text, BBHnet paragraph; App. B.5 ensemble)     -> bbhnet_forward
+ *   - time-series outputs are used "fully online": only the most recent
+ *     floor(f_s/r) predicted samples of each window are kept (App. B.2) and
+ *     subtracted from the strain (App. B.4, client pipeline)
+ *   - DeepClean is retrained on recent data on a single GPU (main text,
+ *     retraining paragraph)                                -> deepclean_backward
+ *
+ * Conventions (all calls):
+ *   - Layout is channel-major, time-contiguous: a window is [C][W] float32,
+ *     a batch is [n][C][W].  Parameters are one flat float32 vector in the
+ *     order documented at gw_model_create.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory read before the call returns.
+ *   - Work is enqueued asynchronously on `hip_stream` (a hipStream_t, NULL =
+ *     the default stream).  Device buffers must stay valid until that work
+ *     completes.  Calls on one pool or one model must be serialised by the
+ *     caller (one host thread, or external locking).
+ *   - Every call validates all of its arguments before enqueueing anything;
+ *     an invalid call returns a nonzero status and leaves all state
+ *     untouched.  No C++ exception crosses the ABI.  gw_last_error() returns
+ *     a thread-local message describing the last failure.
+ *   - The library never allocates device memory after gw_pool_init: ring
+ *     state lives in a caller-provided arena, packed weights in a
+ *     caller-provided buffer and temporaries in caller-provided workspaces
+ *     whose sizes the *_workspace queries return.
+ */
+#ifndef GWSTREAM_H
+#define GWSTREAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GW_OK 0
+#define GW_EINVAL 1        /* null pointer, bad shape/stride/size, duplicate slot */
+#define GW_ENOMEM 2        /* arena or slot table full (admission control)       */
+#define GW_ESTATE 3        /* closed slot, wrong model kind, mismatched state    */
+#define GW_EHIP 4          /* a HIP runtime error; message from the runtime      */
+#define GW_EUNSUPPORTED 5  /* precision or shape without a compiled kernel       */
+
+/* ---- enums ------------------------------------------------------------- */
+#define GW_FP32 0          /* FP32 direct convolution on the vector ALUs        */
+#define GW_BF16 1          /* BF16 MFMA implicit GEMM, FP32 accumulate/epilogue */
+
+#define GW_MODEL_DEEPCLEAN 1
+#define GW_MODEL_BBHNET 2
+
+#define GW_TRAIN 1u        /* deepclean_forward: batch-statistics normalisation,
+                              save what deepclean_backward needs into ws      */
+#define GW_RECOMPUTE 2u    /* with GW_TRAIN: save only checkpoints, recompute
+                              the rest in deepclean_backward                   */
+
+#define GW_LAYER_CONV 0
+#define GW_LAYER_CONVT 1
+#define GW_LAYER_BN_TANH 1 /* layer flag: BatchNorm then tanh after the conv */
+
+typedef struct gw_pool gw_pool;
+typedef struct gw_model gw_model;
+
+/* Thread-local description of the last failed call ("" if none). */
+const char* gw_last_error(void);
+
+/* ---- snapshot pool ---------------------------------------------------- */
+/*
+ * gw_pool_init: create a pool of per-stream snapshot rings inside the
+ * caller-owned device arena `dev_arena` of `bytes` bytes (256-byte aligned).
+ * `max_slots` bounds the number of concurrently open streams and
+ * `max_items` the number of items one batched call may carry.  The pool keeps
+ * a small part of the arena for per-call item tables and allocates a pinned
+ * host staging area of its own (released by gw_pool_free).  The arena must
+ * outlive the pool.  Returns GW_EINVAL on null/misaligned/too-small input.
+ */
+int gw_pool_init(void* dev_arena, size_t bytes, int32_t max_slots, int32_t max_items,
+                 gw_pool** out);
+int gw_pool_free(gw_pool* pool);
+
+/*
+ * gw_stream_open: admit one stream of C channels and window W samples.
+ * Reserves C*W float32 ring samples plus a C*W bfloat16 shadow copy (6*C*W
+ * bytes, rounded up to 256) and zero-fills them on `hip_stream` (the snapshot
+ * before any request is all zeros).  Writes the slot id to *slot.  Returns
+ * GW_ENOMEM, with no state change, when the arena or the slot table has no
+ * room: the caller's admission control queues the stream and retries after a
+ * gw_stream_close.
+ */
+int gw_stream_open(gw_pool* pool, int32_t C, int32_t W, void* hip_stream, int32_t* slot);
+/* Release a slot; its memory is reused by later opens (after pending work). */
+int gw_stream_close(gw_pool* pool, int32_t slot);
+/* Query a slot: channels, window, samples received so far (host-side state). */
+int gw_stream_info(const gw_pool* pool, int32_t slot, int32_t* C, int32_t* W, int64_t* n_seen);
+/*
+ * gw_stream_window (window fetch): copy the slot's current snapshot, oldest
+ * sample first, into out (device [C][W] float32, exact) and/or out_bf16
+ * (device [C][W] uint16 bit patterns of the bfloat16 shadow).  Either may be
+ * NULL.  Used to export stream state and by tests.
+ */
+int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_t* out_bf16, void* hip_stream);
+/* Pool occupancy: bytes in use by rings and bytes still free for rings. */
+int gw_pool_usage(const gw_pool* pool, size_t* used, size_t* free_bytes);
+
+/*
+ * snapshot_update (App. B.1): for each item i < n, append the strictly new
+ * samples of stream slots[i] to its snapshot so that it holds the most recent
+ * W samples:  S <- last W samples of (S ++ X_i).
+ *   slots   host [n]  open slot ids, each at most once per call
+ *   strides host [n]  s_i = number of new samples, 1 <= s_i <= W_i
+ *   samples device    float32; item i's block is [C_i][s_i] (channel-major)
+ *                     starting at element offsets[i]
+ *   offsets host [n]  element offsets into `samples`
+ * Updates of one stream are applied in call order (requests of a stream are
+ * sequential); items of different streams in one call run in parallel.  The
+ * FP32 ring is an exact copy; the BF16 shadow holds round-to-nearest-even
+ * copies for the BF16 path.  All items are validated before any launch.
+ */
+int snapshot_update(gw_pool* pool, int32_t n, const int32_t* slots, const int32_t* strides,
+                    const float* samples, const int64_t* offsets, void* hip_stream);
+
+/* ---- models ------------------------------------------------------------ */
+/*
+ * Network description `desc` (host int32):
+ *   GW_MODEL_DEEPCLEAN: desc[0] = L (number of layers), then 8 ints per layer:
+ *       {type (GW_LAYER_CONV|GW_LAYER_CONVT), C_in, C_out, k, stride, pad,
+ *        out_pad, flags (GW_LAYER_BN_TANH or 0)}
+ *     with C_in of layer l+1 == C_out of layer l, 1 <= k <= 7, stride 1 or 2,
+ *     0 <= pad < k, the last layer C_out == 1 and without BN.  The reference
+ *     network is 21->8->16->32->64 strided convs (k7 s2 p3, BN+tanh), then
+ *     64->32->16->8->8 transposed convs (k7 s2 p3 op1, BN+tanh), then an 8->1
+ *     k7 s1 p3 linear conv.  Conv weights are [C_out][C_in][k] and transposed
+ *     weights [C_in][C_out][k] (cross-correlation, PyTorch layouts).
+ *     Parameter order per layer: weight, bias, then with BN: gamma, beta,
+ *     running mean, running variance (eps = 1e-5).
+ *   GW_MODEL_BBHNET: desc[0] = number of stages S, desc[1] = input channels,
+ *     desc[2..S+1] = output channels of each stage.  Stage = conv_a (k7 s2 p3)
+ *     + ReLU, conv_b (k7 s1 p3), 1x1 stride-2 projection shortcut, add, ReLU;
+ *     then global average pooling and Linear(C_last -> 1).  Parameter order:
+ *     per stage wa, ba, wb, bb, ws, bs (conv layouts), then head w [C_last], b.
+ *
+ * gw_model_packed_bytes: bytes of the caller-owned device buffer that
+ * gw_model_create fills with derived data (folded normalisation, BF16 weight
+ * tiles).  gw_model_create validates `desc` and `n_params`, keeps pointers to
+ * `dev_params` (which must outlive the model) and enqueues the packing
+ * kernels on `hip_stream`.  After the caller changes dev_params (a training
+ * step), gw_model_refresh re-derives the packed data.
+ */
+int gw_model_packed_bytes(int32_t kind, const int32_t* desc, int32_t desc_len, size_t* bytes);
+int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_len, const float* dev_params,
+                    int64_t n_params, void* dev_packed, size_t packed_bytes, void* hip_stream,
+                    gw_model** out);
+int gw_model_refresh(gw_model* model, void* hip_stream);
+int gw_model_free(gw_model* model);
+/* Number of float32 parameters a description implies. */
+int gw_model_n_params(int32_t kind, const int32_t* desc, int32_t desc_len, int64_t* n_params);
+
+/* ---- DeepClean ------------------------------------------------------- */
+/*
+ * deepclean_workspace: bytes of workspace deepclean_forward needs for a batch
+ * of n windows of W samples at `precision` with `flags`.  With GW_TRAIN the
+ * same workspace carries the saved state into deepclean_backward.
+ */
+int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t precision,
+                        uint32_t flags, size_t* bytes);
+
+/*
+ * deepclean_forward: predicted noise for n witness windows, and the
+ * fully-online cleaned strain.
+ * Input, one of:
+ *   pool != NULL: slots host [n], open slots with C == model C_in and window
+ *                 W (all equal); the windows are the current snapshots;
+ *   x    != NULL: device [n][C_in][W] float32 (offline or training use).
+ * Outputs (any may be NULL):
+ *   noise  device [n][W] float32: the full predicted-noise window;
+ *   clean  device, packed float32: item i's block [s_i] starts at the prefix
+ *          sum of strides[0..i) and holds strain - noise[W - s_i .. W) (App.
+ *          B.2 causal selection, App. B.4 subtraction); needs strides (host
+ *          [n], 1 <= s_i <= W) and strain (device, same packing: the s_i
+ *          newest strain samples of each item).
+ * precision GW_FP32 or GW_BF16.  flags: 0 (inference, running statistics),
+ * GW_TRAIN (batch statistics over n*time per channel; requires x),
+ * GW_TRAIN|GW_RECOMPUTE.  Returns GW_EINVAL if ws_bytes is too small.
+ * W must be a multiple of 16 (four stride-2 stages).
+ */
+int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, const float* x,
+                      int32_t n, int32_t W, const int32_t* strides, const float* strain, float* noise,
+                      float* clean, int32_t precision, uint32_t flags, void* ws, size_t ws_bytes,
+                      void* hip_stream);
+
+/*
+ * deepclean_backward (retraining): gradient of a scalar loss with respect to
+ * the flat parameter vector, given dnoise = dL/dnoise (device [n][W] float32)
+ * for the batch-statistics forward that filled `saved` (the ws of a
+ * deepclean_forward call with GW_TRAIN and the same n, W, x, flags and
+ * precision).  dparams (device, n_params float32) is overwritten, not
+ * accumulated; running-statistics entries get 0.  With GW_RECOMPUTE the
+ * activations are recomputed from checkpoints; the result is bitwise equal
+ * to the stored-activation path.  `scratch` needs deepclean_backward_scratch
+ * bytes.  All reductions have a fixed order (deterministic).
+ */
+int deepclean_backward_scratch(const gw_model* model, int32_t n, int32_t W, uint32_t flags,
+                               size_t* bytes);
+int deepclean_backward(const gw_model* model, int32_t n, int32_t W, const float* x,
+                       const float* dnoise, const void* saved, float* dparams, uint32_t flags,
+                       int32_t precision, void* scratch, size_t scratch_bytes, void* hip_stream);
+
+/*
+ * gw_bandpass_mse: band-passed mean-squared-error training loss,
+ *   L = 1/(n W) sum_i || P (strain_i - noise_i) ||^2,
+ * where P projects each length-W row onto its DFT bins k with
+ * f_lo <= k f_s / W <= f_hi, and dL/dnoise = -2/(n W) P (strain - noise).
+ * strain, noise: device [n][W] float32; loss: device float32 scalar;
+ * dnoise: device [n][W] float32 or NULL.  ws: gw_bandpass_workspace bytes.
+ */
+int gw_bandpass_workspace(int32_t n, int32_t W, float fs, float f_lo, float f_hi, size_t* bytes);
+int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float f_hi, const float* strain,
+                    const float* noise, float* loss, float* dnoise, void* ws, size_t ws_bytes,
+                    void* hip_stream);
+
+/* ---- BBHnet ---------------------------------------------------------- */
+/*
+ * bbhnet_forward: one logit (event likelihood score) per window.
+ * Input, one of: pool slots (host [n], C == model C_in, window W) or dense
+ * x device [n][C_in][W].  logits: device [n] float32.  W must be a multiple
+ * of 2^S (S stride-2 stages).  ws: bbhnet_workspace bytes.
+ */
+int bbhnet_workspace(const gw_model* model, int32_t n, int32_t W, int32_t precision, size_t* bytes);
+int bbhnet_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, const float* x,
+                   int32_t n, int32_t W, float* logits, int32_t precision, void* ws,
+                   size_t ws_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWSTREAM_H */

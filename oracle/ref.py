@@ -65,7 +65,8 @@ def conv1d(x, w, b, stride, pad):
     y = np.zeros((B, co, lout), np.float64)
     for j in range(k):
         cols = xp[:, :, j: j + stride * (lout - 1) + 1: stride]  # [B][ci][lout]
-        y += np.einsum("oi,bit->bot", w[:, :, j], cols, optimize=True)
+        # sum over C_in of w[:, :, j] with the tap-j columns, as one matrix product
+        y += np.tensordot(w[:, :, j], cols, axes=([1], [1])).transpose(1, 0, 2)
     if b is not None:
         y += np.asarray(b, np.float64)[None, :, None]
     return y
@@ -82,8 +83,8 @@ def conv_transpose1d(x, w, b, stride, pad, out_pad):
     lout = (L - 1) * stride - 2 * pad + k + out_pad
     full = np.zeros((B, co, max((L - 1) * stride + k, pad + lout)), np.float64)
     for j in range(k):
-        full[:, :, j: j + stride * (L - 1) + 1: stride] += np.einsum(
-            "io,bit->bot", w[:, :, j], x, optimize=True)
+        full[:, :, j: j + stride * (L - 1) + 1: stride] += np.tensordot(
+            w[:, :, j], x, axes=([0], [1])).transpose(1, 0, 2)
     y = full[:, :, pad: pad + lout].copy()
     if b is not None:
         y += np.asarray(b, np.float64)[None, :, None]

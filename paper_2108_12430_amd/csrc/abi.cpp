@@ -1,0 +1,1184 @@
+// C ABI of libgwstream.so: argument validation, slot/arena bookkeeping,
+// per-call item tables and kernel dispatch.  No kernel arithmetic lives here.
+#include "gwstream.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using gw::Item;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  return fail(GW_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(expr)                              \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+#define CHK(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != GW_OK) return rc_; \
+  } while (0)
+
+inline size_t r256(size_t x) { return (x + 255) & ~size_t(255); }
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Ring of pinned host staging slots for the per-call item tables; each slot
+// is reused only after the copy that last read it has completed.
+struct Stager {
+  static constexpr int K = 32;
+  Item* host = nullptr;
+  Item* dev = nullptr;
+  int cap = 0;
+  int next = 0;
+  hipEvent_t ev[K] = {};
+  bool used[K] = {};
+  static size_t dev_bytes(int cap) { return r256(sizeof(Item) * (size_t)cap * K); }
+  int init(void* dev_region, int cap_items) {
+    cap = cap_items;
+    dev = reinterpret_cast<Item*>(dev_region);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&host), sizeof(Item) * (size_t)cap * K,
+                         hipHostMallocDefault));
+    for (int k = 0; k < K; ++k) HIPCHK(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+    return GW_OK;
+  }
+  void release() {
+    for (int k = 0; k < K; ++k)
+      if (ev[k]) {
+        if (used[k]) (void)hipEventSynchronize(ev[k]);
+        (void)hipEventDestroy(ev[k]);
+        ev[k] = nullptr;
+      }
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+  }
+  int stage(const std::vector<Item>& items, hipStream_t st, const Item** out) {
+    if ((int)items.size() > cap) return fail(GW_EINVAL, "too many items in one call");
+    const int k = next;
+    next = (next + 1) % K;
+    if (used[k]) HIPCHK(hipEventSynchronize(ev[k]));
+    std::memcpy(host + (size_t)k * cap, items.data(), items.size() * sizeof(Item));
+    HIPCHK(hipMemcpyAsync(dev + (size_t)k * cap, host + (size_t)k * cap, items.size() * sizeof(Item),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ev[k], st));
+    used[k] = true;
+    *out = dev + (size_t)k * cap;
+    return GW_OK;
+  }
+};
+
+}  // namespace
+
+// ===========================================================================
+// Pool
+// ===========================================================================
+struct gw_pool {
+  char* arena = nullptr;
+  size_t bytes = 0;
+  int max_slots = 0, max_items = 0;
+  size_t ring_base = 0;
+  Stager stager;
+  struct Slot {
+    bool open = false;
+    int C = 0, W = 0;
+    size_t off = 0, size = 0;
+    int head = 0;
+    int64_t n_seen = 0;
+  };
+  std::vector<Slot> slots;
+  std::map<size_t, size_t> free_;  // offset -> size
+  size_t used = 0;
+
+  static size_t ring_bytes(int C, int W) { return r256((size_t)C * W * 4) + r256((size_t)C * W * 2); }
+  int64_t ring_elem(const Slot& s) const { return (int64_t)(s.off / 4); }
+  int64_t shadow_elem(const Slot& s) const {
+    return (int64_t)((s.off + r256((size_t)s.C * s.W * 4)) / 2);
+  }
+  bool alloc(size_t size, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= size) {
+        *off = it->first;
+        const size_t rest = it->second - size;
+        const size_t noff = it->first + size;
+        free_.erase(it);
+        if (rest) free_[noff] = rest;
+        used += size;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t size) {
+    used -= size;
+    auto it = free_.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int check_slot(int32_t s) const {
+    if (s < 0 || s >= max_slots) return fail(GW_EINVAL, "slot id out of range");
+    if (!slots[s].open) return fail(GW_ESTATE, "slot is not open");
+    return GW_OK;
+  }
+};
+
+extern "C" const char* gw_last_error(void) { return g_err.c_str(); }
+
+extern "C" int gw_pool_init(void* dev_arena, size_t bytes, int32_t max_slots, int32_t max_items,
+                            gw_pool** out) {
+  if (!dev_arena || !out) return fail(GW_EINVAL, "null arena or out pointer");
+  if (reinterpret_cast<uintptr_t>(dev_arena) % 256) return fail(GW_EINVAL, "arena not 256-byte aligned");
+  if (max_slots < 1 || max_items < 1 || max_items > (1 << 16))
+    return fail(GW_EINVAL, "max_slots/max_items out of range");
+  const size_t desc = Stager::dev_bytes(max_items);
+  if (bytes < desc + 256) return fail(GW_EINVAL, "arena too small for the item tables");
+  auto* p = new gw_pool();
+  p->arena = reinterpret_cast<char*>(dev_arena);
+  p->bytes = bytes;
+  p->max_slots = max_slots;
+  p->max_items = max_items;
+  p->ring_base = desc;
+  p->slots.resize(max_slots);
+  const size_t usable = (bytes - desc) & ~size_t(255);
+  if (usable) p->free_[desc] = usable;
+  int rc = p->stager.init(p->arena, max_items);
+  if (rc != GW_OK) {
+    p->stager.release();
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return GW_OK;
+}
+
+extern "C" int gw_pool_free(gw_pool* pool) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  pool->stager.release();
+  delete pool;
+  return GW_OK;
+}
+
+extern "C" int gw_stream_open(gw_pool* pool, int32_t C, int32_t W, void* hip_stream, int32_t* slot) {
+  if (!pool || !slot) return fail(GW_EINVAL, "null pool or slot pointer");
+  if (C < 1 || W < 1 || (int64_t)C * W > (int64_t)1 << 30) return fail(GW_EINVAL, "bad C or W");
+  int id = -1;
+  for (int i = 0; i < pool->max_slots; ++i)
+    if (!pool->slots[i].open) {
+      id = i;
+      break;
+    }
+  if (id < 0) return fail(GW_ENOMEM, "slot table full");
+  const size_t size = gw_pool::ring_bytes(C, W);
+  size_t off = 0;
+  if (!pool->alloc(size, &off)) return fail(GW_ENOMEM, "arena full");
+  hipError_t e = gw::launch_fill_zero(pool->arena + off, size, S(hip_stream));
+  if (e != hipSuccess) {
+    pool->release(off, size);
+    return hip_fail(e, "fill_zero");
+  }
+  auto& s = pool->slots[id];
+  s.open = true;
+  s.C = C;
+  s.W = W;
+  s.off = off;
+  s.size = size;
+  s.head = 0;
+  s.n_seen = 0;
+  *slot = id;
+  return GW_OK;
+}
+
+extern "C" int gw_stream_close(gw_pool* pool, int32_t slot) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  CHK(pool->check_slot(slot));
+  auto& s = pool->slots[slot];
+  pool->release(s.off, s.size);
+  s = gw_pool::Slot();
+  return GW_OK;
+}
+
+extern "C" int gw_stream_info(const gw_pool* pool, int32_t slot, int32_t* C, int32_t* W,
+                              int64_t* n_seen) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  CHK(pool->check_slot(slot));
+  const auto& s = pool->slots[slot];
+  if (C) *C = s.C;
+  if (W) *W = s.W;
+  if (n_seen) *n_seen = s.n_seen;
+  return GW_OK;
+}
+
+extern "C" int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_t* out_bf16,
+                                void* hip_stream) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  CHK(pool->check_slot(slot));
+  if (!out && !out_bf16) return GW_OK;
+  const auto& s = pool->slots[slot];
+  std::vector<Item> items(1);
+  std::memset(&items[0], 0, sizeof(Item));
+  items[0].ring = pool->ring_elem(s);
+  items[0].shadow = pool->shadow_elem(s);
+  items[0].head = s.head;
+  items[0].C = s.C;
+  items[0].W = s.W;
+  const Item* dev = nullptr;
+  CHK(pool->stager.stage(items, S(hip_stream), &dev));
+  HIPCHK(gw::launch_gather(pool->arena, dev, 1, s.C, s.W, out, out_bf16, S(hip_stream)));
+  return GW_OK;
+}
+
+extern "C" int gw_pool_usage(const gw_pool* pool, size_t* used, size_t* free_bytes) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  size_t f = 0;
+  for (auto& kv : pool->free_) f += kv.second;
+  if (used) *used = pool->used;
+  if (free_bytes) *free_bytes = f;
+  return GW_OK;
+}
+
+extern "C" int snapshot_update(gw_pool* pool, int32_t n, const int32_t* slots, const int32_t* strides,
+                               const float* samples, const int64_t* offsets, void* hip_stream) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  if (n == 0) return GW_OK;
+  if (n < 0 || n > pool->max_items) return fail(GW_EINVAL, "n out of range");
+  if (!slots || !strides || !samples || !offsets) return fail(GW_EINVAL, "null argument");
+  std::vector<char> seen(pool->max_slots, 0);
+  std::vector<Item> items(n);
+  int max_cs = 0;
+  for (int i = 0; i < n; ++i) {
+    CHK(pool->check_slot(slots[i]));
+    if (seen[slots[i]]) return fail(GW_EINVAL, "slot appears twice in one call");
+    seen[slots[i]] = 1;
+    const auto& s = pool->slots[slots[i]];
+    if (strides[i] < 1 || strides[i] > s.W) return fail(GW_EINVAL, "stride must be in [1, W]");
+    if (offsets[i] < 0) return fail(GW_EINVAL, "negative sample offset");
+    Item& it = items[i];
+    it.ring = pool->ring_elem(s);
+    it.shadow = pool->shadow_elem(s);
+    it.src = offsets[i];
+    it.out = 0;
+    it.head = s.head;
+    it.s = strides[i];
+    it.C = s.C;
+    it.W = s.W;
+    max_cs = std::max(max_cs, s.C * strides[i]);
+  }
+  const Item* dev = nullptr;
+  CHK(pool->stager.stage(items, S(hip_stream), &dev));
+  HIPCHK(gw::launch_snapshot(pool->arena, dev, n, max_cs, samples, S(hip_stream)));
+  for (int i = 0; i < n; ++i) {
+    auto& s = pool->slots[slots[i]];
+    s.head = (s.head + strides[i]) % s.W;
+    s.n_seen += strides[i];
+  }
+  return GW_OK;
+}
+
+// ===========================================================================
+// Models
+// ===========================================================================
+namespace {
+
+struct LayerD {
+  int type, ci, co, k, s, p, op, bn;
+  int64_t w, b, g, be, m, v;  // parameter offsets (floats)
+  size_t scale, shift;        // packed byte offsets
+  size_t wbf;                 // packed bf16 weights byte offset
+  bool bf16;                  // BF16 kernel available
+};
+
+struct StageD {
+  int ci, co;
+  int64_t wa, ba, wb, bb, ws, bs;
+  size_t wa_bf, wb_bf;
+  bool bf16;
+};
+
+constexpr int DENSE_ITEMS = 4096;  // item-table capacity for dense-input calls
+
+}  // namespace
+
+struct gw_model {
+  int kind = 0;
+  std::vector<LayerD> layers;
+  std::vector<StageD> stages;
+  int c_in = 0, c_last = 0;
+  int64_t head_w = 0, head_b = 0;
+  int64_t n_params = 0;
+  size_t packed_bytes = 0;
+  const float* params = nullptr;
+  char* packed = nullptr;
+  Stager stager;
+  bool bf16_all = false;
+};
+
+namespace {
+
+int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
+  if (!desc || len < 1) return fail(GW_EINVAL, "null or empty description");
+  m.kind = kind;
+  int64_t off = 0;
+  size_t pk = 0;
+  if (kind == GW_MODEL_DEEPCLEAN) {
+    const int L = desc[0];
+    if (L < 1 || L > 64 || len != 1 + 8 * L) return fail(GW_EINVAL, "bad DeepClean description length");
+    pk = Stager::dev_bytes(DENSE_ITEMS);
+    m.bf16_all = true;
+    for (int l = 0; l < L; ++l) {
+      const int32_t* d = desc + 1 + 8 * l;
+      LayerD ly{};
+      ly.type = d[0];
+      ly.ci = d[1];
+      ly.co = d[2];
+      ly.k = d[3];
+      ly.s = d[4];
+      ly.p = d[5];
+      ly.op = d[6];
+      ly.bn = d[7];
+      if (ly.type != GW_LAYER_CONV && ly.type != GW_LAYER_CONVT) return fail(GW_EINVAL, "bad layer type");
+      if (ly.ci < 1 || ly.co < 1 || ly.ci > 4096 || ly.co > 4096) return fail(GW_EINVAL, "bad channel count");
+      if (ly.k < 1 || ly.k > 7) return fail(GW_EUNSUPPORTED, "kernel size must be 1..7");
+      if (ly.s != 1 && ly.s != 2) return fail(GW_EUNSUPPORTED, "stride must be 1 or 2");
+      if (ly.p < 0 || ly.p >= ly.k) return fail(GW_EINVAL, "pad must be in [0, k)");
+      if (ly.op < 0 || ly.op >= ly.s || (ly.type == GW_LAYER_CONV && ly.op))
+        return fail(GW_EINVAL, "bad output padding");
+      if (ly.bn != 0 && ly.bn != GW_LAYER_BN_TANH) return fail(GW_EINVAL, "bad layer flags");
+      if (l > 0 && ly.ci != m.layers.back().co) return fail(GW_EINVAL, "channel chain mismatch");
+      ly.w = off;
+      off += (int64_t)ly.ci * ly.co * ly.k;
+      ly.b = off;
+      off += ly.co;
+      if (ly.bn) {
+        ly.g = off;
+        ly.be = off + ly.co;
+        ly.m = off + 2 * ly.co;
+        ly.v = off + 3 * ly.co;
+        off += 4 * ly.co;
+      }
+      ly.scale = pk;
+      pk += r256(sizeof(float) * ly.co);
+      ly.shift = pk;
+      pk += r256(sizeof(float) * ly.co);
+      m.layers.push_back(ly);
+    }
+    if (m.layers.back().co != 1 || m.layers.back().bn)
+      return fail(GW_EINVAL, "last layer must have one output channel and no normalisation");
+    for (auto& ly : m.layers) {
+      ly.bf16 = gw::conv_bf16_supported(ly.ci, ly.co, ly.k, ly.s, ly.type == GW_LAYER_CONVT);
+      if (ly.bf16) {
+        ly.wbf = pk;
+        pk += r256(2 * gw::conv_bf16_packed_elems(ly.ci, ly.co, ly.k, ly.type == GW_LAYER_CONVT));
+      }
+      m.bf16_all = m.bf16_all && ly.bf16;
+    }
+    m.c_in = m.layers[0].ci;
+  } else if (kind == GW_MODEL_BBHNET) {
+    const int Sn = desc[0];
+    if (Sn < 1 || Sn > 8 || len != 2 + Sn) return fail(GW_EINVAL, "bad BBHnet description length");
+    m.c_in = desc[1];
+    if (m.c_in < 1 || m.c_in > 1024) return fail(GW_EINVAL, "bad input channels");
+    int ci = m.c_in;
+    m.bf16_all = true;
+    for (int s = 0; s < Sn; ++s) {
+      StageD sd{};
+      sd.ci = ci;
+      sd.co = desc[2 + s];
+      if (sd.co < 1 || sd.co > 1024) return fail(GW_EINVAL, "bad stage channels");
+      sd.wa = off;
+      off += (int64_t)sd.co * sd.ci * 7;
+      sd.ba = off;
+      off += sd.co;
+      sd.wb = off;
+      off += (int64_t)sd.co * sd.co * 7;
+      sd.bb = off;
+      off += sd.co;
+      sd.ws = off;
+      off += (int64_t)sd.co * sd.ci;
+      sd.bs = off;
+      off += sd.co;
+      sd.bf16 = gw::conv_bf16_supported(sd.ci, sd.co, 7, 2, false) &&
+                gw::conv_bf16_supported(sd.co, sd.co, 7, 1, false);
+      if (sd.bf16) {
+        sd.wa_bf = pk;
+        pk += r256(2 * gw::conv_bf16_packed_elems(sd.ci, sd.co, 7, false));
+        sd.wb_bf = pk;
+        pk += r256(2 * gw::conv_bf16_packed_elems(sd.co, sd.co, 7, false));
+      }
+      m.bf16_all = m.bf16_all && sd.bf16;
+      m.stages.push_back(sd);
+      ci = sd.co;
+    }
+    m.c_last = ci;
+    m.head_w = off;
+    off += ci;
+    m.head_b = off;
+    off += 1;
+    pk = std::max<size_t>(pk, 256);
+  } else {
+    return fail(GW_EINVAL, "unknown model kind");
+  }
+  m.n_params = off;
+  m.packed_bytes = pk;
+  return GW_OK;
+}
+
+int pack_model(gw_model* m, hipStream_t st) {
+  const float* P = m->params;
+  if (m->kind == GW_MODEL_DEEPCLEAN) {
+    for (auto& ly : m->layers) {
+      float* sc = reinterpret_cast<float*>(m->packed + ly.scale);
+      float* sh = reinterpret_cast<float*>(m->packed + ly.shift);
+      HIPCHK(gw::launch_fold_bn(P + ly.b, ly.bn ? P + ly.g : nullptr, ly.bn ? P + ly.be : nullptr,
+                                ly.bn ? P + ly.m : nullptr, ly.bn ? P + ly.v : nullptr, sc, sh, ly.co,
+                                st));
+      if (ly.bf16)
+        HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf), ly.ci,
+                                    ly.co, ly.k, ly.type == GW_LAYER_CONVT, st));
+    }
+  } else {
+    for (auto& sd : m->stages) {
+      if (!sd.bf16) continue;
+      HIPCHK(gw::launch_pack_bf16(P + sd.wa, reinterpret_cast<uint16_t*>(m->packed + sd.wa_bf), sd.ci,
+                                  sd.co, 7, false, st));
+      HIPCHK(gw::launch_pack_bf16(P + sd.wb, reinterpret_cast<uint16_t*>(m->packed + sd.wb_bf), sd.co,
+                                  sd.co, 7, false, st));
+    }
+  }
+  return GW_OK;
+}
+
+int layer_lout(const LayerD& ly, int L) {
+  if (ly.type == GW_LAYER_CONV) {
+    if (L + 2 * ly.p < ly.k) return -1;
+    return (L + 2 * ly.p - ly.k) / ly.s + 1;
+  }
+  return (L - 1) * ly.s - 2 * ly.p + ly.k + ly.op;
+}
+
+// Per-layer input/output lengths for a window of W samples; error unless the
+// network maps W back to W.
+int dc_lengths(const gw_model* m, int W, std::vector<int>& lin, std::vector<int>& lout) {
+  lin.clear();
+  lout.clear();
+  int L = W;
+  for (auto& ly : m->layers) {
+    lin.push_back(L);
+    L = layer_lout(ly, L);
+    if (L < 1) return fail(GW_EINVAL, "window too short for the network");
+    lout.push_back(L);
+  }
+  if (L != W) return fail(GW_EINVAL, "network does not map W samples back to W (W must be a multiple of the total stride)");
+  return GW_OK;
+}
+
+}  // namespace
+
+extern "C" int gw_model_n_params(int32_t kind, const int32_t* desc, int32_t desc_len, int64_t* n) {
+  if (!n) return fail(GW_EINVAL, "null out pointer");
+  gw_model m;
+  CHK(build_layout(kind, desc, desc_len, m));
+  *n = m.n_params;
+  return GW_OK;
+}
+
+extern "C" int gw_model_packed_bytes(int32_t kind, const int32_t* desc, int32_t desc_len, size_t* bytes) {
+  if (!bytes) return fail(GW_EINVAL, "null out pointer");
+  gw_model m;
+  CHK(build_layout(kind, desc, desc_len, m));
+  *bytes = m.packed_bytes;
+  return GW_OK;
+}
+
+extern "C" int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_len,
+                               const float* dev_params, int64_t n_params, void* dev_packed,
+                               size_t packed_bytes, void* hip_stream, gw_model** out) {
+  if (!out || !dev_params || !dev_packed) return fail(GW_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(dev_packed) % 256) return fail(GW_EINVAL, "packed buffer not 256-byte aligned");
+  auto* m = new gw_model();
+  int rc = build_layout(kind, desc, desc_len, *m);
+  if (rc == GW_OK && n_params != m->n_params) rc = fail(GW_EINVAL, "n_params does not match the description");
+  if (rc == GW_OK && packed_bytes < m->packed_bytes) rc = fail(GW_EINVAL, "packed buffer too small");
+  if (rc != GW_OK) {
+    delete m;
+    return rc;
+  }
+  m->params = dev_params;
+  m->packed = reinterpret_cast<char*>(dev_packed);
+  if (kind == GW_MODEL_DEEPCLEAN) rc = m->stager.init(m->packed, DENSE_ITEMS);
+  if (rc == GW_OK) rc = pack_model(m, S(hip_stream));
+  if (rc != GW_OK) {
+    m->stager.release();
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return GW_OK;
+}
+
+extern "C" int gw_model_refresh(gw_model* m, void* hip_stream) {
+  if (!m) return fail(GW_EINVAL, "null model");
+  return pack_model(m, S(hip_stream));
+}
+
+extern "C" int gw_model_free(gw_model* m) {
+  if (!m) return fail(GW_EINVAL, "null model");
+  m->stager.release();
+  delete m;
+  return GW_OK;
+}
+
+// ===========================================================================
+// DeepClean
+// ===========================================================================
+namespace {
+
+struct DcWs {
+  // inference
+  size_t buf[2] = {0, 0};
+  size_t total = 0;
+  // training
+  std::vector<size_t> mean, invstd, z, a;  // per layer (SIZE_MAX = none)
+  size_t ztmp = 0, atmp[2] = {0, 0};
+  size_t partial = 0;
+  int ckpt = -1;
+};
+
+constexpr size_t NONE = ~size_t(0);
+
+int dc_ws_layout(const gw_model* m, int n, int W, int precision, uint32_t flags, DcWs& w) {
+  std::vector<int> lin, lout;
+  CHK(dc_lengths(m, W, lin, lout));
+  const int L = (int)m->layers.size();
+  const size_t esz = 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += r256(bytes);
+    return o;
+  };
+  if (!(flags & GW_TRAIN)) {
+    size_t mx = 256;
+    for (int l = 0; l + 1 < L; ++l)
+      mx = std::max(mx, (size_t)n * m->layers[l].co * lout[l] * esz);
+    w.buf[0] = take(mx);
+    w.buf[1] = take(mx);
+    w.total = off;
+    (void)precision;
+    return GW_OK;
+  }
+  const bool rec = flags & GW_RECOMPUTE;
+  // checkpoint: the layer with the shortest output (the bottleneck)
+  int ck = 0;
+  for (int l = 0; l + 1 < L; ++l)
+    if (lout[l] < lout[ck]) ck = l;
+  w.ckpt = rec ? ck : -1;
+  w.mean.assign(L, NONE);
+  w.invstd.assign(L, NONE);
+  w.z.assign(L, NONE);
+  w.a.assign(L, NONE);
+  for (int l = 0; l < L; ++l)
+    if (m->layers[l].bn) {
+      w.mean[l] = take(4 * m->layers[l].co);
+      w.invstd[l] = take(4 * m->layers[l].co);
+    }
+  size_t mx = 256;
+  int maxc = 1, maxchunk = 1;
+  for (int l = 0; l + 1 < L; ++l) {
+    const size_t sz = (size_t)n * m->layers[l].co * lout[l] * esz;
+    mx = std::max(mx, sz);
+    maxc = std::max(maxc, m->layers[l].co);
+    maxchunk = std::max(maxchunk, gw::red_chunks(n, lout[l]));
+    if (!rec) {
+      if (m->layers[l].bn) w.z[l] = take(sz);
+      w.a[l] = take(sz);
+    } else if (l == ck) {
+      w.a[l] = take(sz);
+    }
+  }
+  if (rec) {
+    w.ztmp = take(mx);
+    w.atmp[0] = take(mx);
+    w.atmp[1] = take(mx);
+  }
+  w.partial = take((size_t)maxc * maxchunk * 2 * sizeof(double));
+  w.total = off;
+  return GW_OK;
+}
+
+gw::ConvP conv_params(const gw_model* m, const LayerD& ly, int n, int Lin, int Lout) {
+  gw::ConvP p{};
+  p.n = n;
+  p.Ci = ly.ci;
+  p.Co = ly.co;
+  p.Lin = Lin;
+  p.Lout = Lout;
+  p.k = ly.k;
+  p.stride = ly.s;
+  p.pad = ly.p;
+  p.w = m->params + ly.w;
+  if (ly.type == GW_LAYER_CONV) {
+    p.wso = (int64_t)ly.ci * ly.k;
+    p.wsi = ly.k;
+  } else {
+    p.wsi = (int64_t)ly.co * ly.k;
+    p.wso = ly.k;
+  }
+  p.bias = m->params + ly.b;
+  p.scale = reinterpret_cast<const float*>(m->packed + ly.scale);
+  p.shift = reinterpret_cast<const float*>(m->packed + ly.shift);
+  if (ly.bf16) p.wpk = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf);
+  return p;
+}
+
+hipError_t run_conv(const gw::ConvP& p, const LayerD& ly, int epi, int src, int precision,
+                    hipStream_t st) {
+  const bool tr = ly.type == GW_LAYER_CONVT;
+  if (precision == GW_BF16) return gw::launch_conv_bf16(p, tr, epi, src, st);
+  return gw::launch_conv_fp32(p, tr, epi, src, st);
+}
+
+}  // namespace
+
+extern "C" int deepclean_workspace(const gw_model* m, int32_t n, int32_t W, int32_t precision,
+                                   uint32_t flags, size_t* bytes) {
+  if (!m || !bytes) return fail(GW_EINVAL, "null argument");
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  if (n < 1) return fail(GW_EINVAL, "n must be >= 1");
+  DcWs w;
+  CHK(dc_ws_layout(m, n, W, precision, flags, w));
+  *bytes = w.total;
+  return GW_OK;
+}
+
+extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x,
+                                 int32_t n, int32_t W, const int32_t* strides, const float* strain,
+                                 float* noise, float* clean, int32_t precision, uint32_t flags,
+                                 void* ws, size_t ws_bytes, void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  if (n == 0) return GW_OK;
+  if (n < 0) return fail(GW_EINVAL, "negative n");
+  if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
+  if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
+  if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
+  if (flags & ~(GW_TRAIN | GW_RECOMPUTE)) return fail(GW_EINVAL, "bad flags");
+  if ((flags & GW_RECOMPUTE) && !(flags & GW_TRAIN)) return fail(GW_EINVAL, "GW_RECOMPUTE needs GW_TRAIN");
+  if ((flags & GW_TRAIN) && !x) return fail(GW_EINVAL, "training forward needs dense input x");
+  if ((flags & GW_TRAIN) && precision != GW_FP32) return fail(GW_EUNSUPPORTED, "training path is FP32");
+  if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
+  if (clean && (!strides || !strain)) return fail(GW_EINVAL, "clean output needs strides and strain");
+  if (!ws) return fail(GW_EINVAL, "null workspace");
+  DcWs w;
+  CHK(dc_ws_layout(m, n, W, precision, flags, w));
+  if (ws_bytes < w.total)
+    return fail(GW_EINVAL, "workspace too small: need " + std::to_string(w.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GW_EINVAL, "workspace not 256-byte aligned");
+  std::vector<int> lin, lout;
+  CHK(dc_lengths(m, W, lin, lout));
+
+  // item table: ring addresses (pool input) and stride/offset of the clean block
+  const bool need_items = pool || clean;
+  std::vector<Item> items;
+  if (need_items) {
+    items.resize(n);
+    std::vector<char> seen(pool ? pool->max_slots : 0, 0);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      Item& it = items[i];
+      std::memset(&it, 0, sizeof(it));
+      if (pool) {
+        CHK(pool->check_slot(slots[i]));
+        if (seen[slots[i]]) return fail(GW_EINVAL, "slot appears twice in one call");
+        seen[slots[i]] = 1;
+        const auto& s = pool->slots[slots[i]];
+        if (s.C != m->c_in || s.W != W) return fail(GW_EINVAL, "slot C/W does not match the model and W");
+        it.ring = pool->ring_elem(s);
+        it.shadow = pool->shadow_elem(s);
+        it.head = s.head;
+        it.C = s.C;
+        it.W = s.W;
+      }
+      if (clean) {
+        if (strides[i] < 1 || strides[i] > W) return fail(GW_EINVAL, "stride must be in [1, W]");
+        it.s = strides[i];
+        it.out = off;
+        off += strides[i];
+      } else {
+        it.s = 0;
+      }
+    }
+  }
+  const Item* dev_items = nullptr;
+  if (need_items) {
+    if (pool)
+      CHK(pool->stager.stage(items, st, &dev_items));
+    else
+      CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items));
+  }
+
+  char* wsb = reinterpret_cast<char*>(ws);
+  const int L = (int)m->layers.size();
+  const void* arena = pool ? pool->arena : nullptr;
+  if (!(flags & GW_TRAIN)) {
+    const float* in = x;
+    for (int l = 0; l < L; ++l) {
+      const LayerD& ly = m->layers[l];
+      gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
+      p.items = dev_items;
+      p.arena = arena;
+      p.x = in;
+      const int src = (l == 0 && pool) ? gw::SRC_RING : gw::SRC_DENSE;
+      int epi;
+      if (l == L - 1) {
+        epi = gw::EPI_OUT;
+        p.noise = noise;
+        p.clean = clean;
+        p.strain = strain;
+      } else {
+        epi = ly.bn ? gw::EPI_AFFINE_TANH : gw::EPI_AFFINE;
+        p.y = reinterpret_cast<float*>(wsb + w.buf[l & 1]);
+        p.yh = reinterpret_cast<uint16_t*>(wsb + w.buf[l & 1]);
+      }
+      if (precision == GW_BF16 && l > 0) p.xh = reinterpret_cast<const uint16_t*>(in);
+      HIPCHK(run_conv(p, ly, epi, src, precision, st));
+      in = p.y;
+    }
+    return GW_OK;
+  }
+  // training forward: z = conv(a) + b, batch statistics, a = tanh(BN(z))
+  double* partial = reinterpret_cast<double*>(wsb + w.partial);
+  const float* in = x;
+  for (int l = 0; l < L; ++l) {
+    const LayerD& ly = m->layers[l];
+    gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
+    p.items = dev_items;
+    p.x = in;
+    if (l == L - 1) {
+      p.noise = noise;
+      p.clean = clean;
+      p.strain = strain;
+      HIPCHK(run_conv(p, ly, gw::EPI_OUT, gw::SRC_DENSE, GW_FP32, st));
+      break;
+    }
+    float* z = reinterpret_cast<float*>(wsb + (w.ckpt >= 0 ? w.ztmp : (ly.bn ? w.z[l] : w.a[l])));
+    float* a;
+    if (w.ckpt < 0)
+      a = reinterpret_cast<float*>(wsb + w.a[l]);
+    else if (l == w.ckpt)
+      a = reinterpret_cast<float*>(wsb + w.a[l]);
+    else
+      a = reinterpret_cast<float*>(wsb + w.atmp[l & 1]);
+    if (!ly.bn) z = a;
+    p.y = z;
+    HIPCHK(run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+    if (ly.bn) {
+      float* mean = reinterpret_cast<float*>(wsb + w.mean[l]);
+      float* invstd = reinterpret_cast<float*>(wsb + w.invstd[l]);
+      HIPCHK(gw::launch_bn_stats(z, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]), mean, invstd, st));
+      HIPCHK(gw::launch_bn_apply_tanh(z, mean, invstd, m->params + ly.g, m->params + ly.be, a, n, ly.co,
+                                      lout[l], st));
+    }
+    in = a;
+  }
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BwWs {
+  size_t g[2] = {0, 0};
+  size_t dz = 0;
+  std::vector<size_t> z, a;  // recomputed activations (recompute mode)
+  size_t partial = 0;
+  size_t wg = 0;
+  size_t total = 0;
+};
+
+int bw_layout(const gw_model* m, int n, int W, uint32_t flags, BwWs& b) {
+  std::vector<int> lin, lout;
+  CHK(dc_lengths(m, W, lin, lout));
+  const int L = (int)m->layers.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += r256(bytes);
+    return o;
+  };
+  size_t mx = 256, mxin = 256, mwg = 256;
+  int maxc = 1, maxchunk = 1;
+  for (int l = 0; l < L; ++l) {
+    const auto& ly = m->layers[l];
+    mx = std::max(mx, (size_t)n * ly.co * lout[l] * 4);
+    if (l > 0) mxin = std::max(mxin, (size_t)n * ly.ci * lin[l] * 4);
+    maxc = std::max(maxc, ly.co);
+    maxchunk = std::max(maxchunk, gw::red_chunks(n, lout[l]));
+    const bool tr = ly.type == GW_LAYER_CONVT;
+    const int Lp = tr ? lin[l] : lout[l];
+    mwg = std::max(mwg, gw::wgrad_scratch_bytes(n, Lp, ly.ci * ly.co * ly.k));
+  }
+  b.g[0] = take(mxin);
+  b.g[1] = take(mxin);
+  b.dz = take(mx);
+  b.z.assign(L, NONE);
+  b.a.assign(L, NONE);
+  if (flags & GW_RECOMPUTE) {
+    // The two segments (up to and including the checkpoint layer, and after
+    // it) are recomputed one at a time, so they share one region.
+    int ck = 0;
+    for (int l = 0; l + 1 < L; ++l)
+      if (lout[l] < lout[ck]) ck = l;
+    const size_t base = off;
+    size_t seg_end[2] = {base, base};
+    for (int l = 0; l + 1 < L; ++l) {
+      size_t& e = seg_end[l <= ck ? 0 : 1];
+      const size_t sz = r256((size_t)n * m->layers[l].co * lout[l] * 4);
+      if (m->layers[l].bn) {
+        b.z[l] = e;
+        e += sz;
+      }
+      b.a[l] = e;
+      e += sz;
+    }
+    off = std::max(seg_end[0], seg_end[1]);
+  }
+  b.partial = take((size_t)maxc * maxchunk * 2 * sizeof(double));
+  b.wg = take(mwg);
+  b.total = off;
+  return GW_OK;
+}
+
+}  // namespace
+
+extern "C" int deepclean_backward_scratch(const gw_model* m, int32_t n, int32_t W, uint32_t flags,
+                                          size_t* bytes) {
+  if (!m || !bytes) return fail(GW_EINVAL, "null argument");
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  if (n < 1) return fail(GW_EINVAL, "n must be >= 1");
+  BwWs b;
+  CHK(bw_layout(m, n, W, flags, b));
+  *bytes = b.total;
+  return GW_OK;
+}
+
+extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const float* x,
+                                  const float* dnoise, const void* saved, float* dparams,
+                                  uint32_t flags, int32_t precision, void* scratch,
+                                  size_t scratch_bytes, void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  if (n < 1) return fail(GW_EINVAL, "n must be >= 1");
+  if (!x || !dnoise || !saved || !dparams || !scratch) return fail(GW_EINVAL, "null argument");
+  if (!(flags & GW_TRAIN) || (flags & ~(GW_TRAIN | GW_RECOMPUTE)))
+    return fail(GW_EINVAL, "flags must be GW_TRAIN or GW_TRAIN|GW_RECOMPUTE (as in the forward)");
+  if (precision != GW_FP32) return fail(GW_EUNSUPPORTED, "training path is FP32");
+  DcWs w;
+  CHK(dc_ws_layout(m, n, W, precision, flags, w));
+  BwWs b;
+  CHK(bw_layout(m, n, W, flags, b));
+  if (scratch_bytes < b.total)
+    return fail(GW_EINVAL, "scratch too small: need " + std::to_string(b.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(scratch) % 256 || reinterpret_cast<uintptr_t>(saved) % 256)
+    return fail(GW_EINVAL, "saved/scratch not 256-byte aligned");
+  std::vector<int> lin, lout;
+  CHK(dc_lengths(m, W, lin, lout));
+  const int L = (int)m->layers.size();
+  const char* sv = reinterpret_cast<const char*>(saved);
+  char* sc = reinterpret_cast<char*>(scratch);
+  double* partial = reinterpret_cast<double*>(sc + b.partial);
+  const bool rec = flags & GW_RECOMPUTE;
+  auto savedf = [&](size_t off) { return reinterpret_cast<const float*>(sv + off); };
+  auto scf = [&](size_t off) { return reinterpret_cast<float*>(sc + off); };
+
+  std::vector<const float*> Z(L, nullptr), A(L, nullptr);
+  if (rec) A[w.ckpt] = savedf(w.a[w.ckpt]);
+  if (!rec)
+    for (int l = 0; l + 1 < L; ++l) {
+      A[l] = savedf(w.a[l]);
+      Z[l] = m->layers[l].bn ? savedf(w.z[l]) : A[l];
+    }
+  // recompute layers [l0, l1] from `in` with the saved statistics
+  auto recompute = [&](int l0, int l1, const float* in) -> int {
+    for (int l = l0; l <= l1; ++l) {
+      const LayerD& ly = m->layers[l];
+      gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
+      p.x = in;
+      float* a = scf(b.a[l]);
+      float* z = ly.bn ? scf(b.z[l]) : a;
+      p.y = z;
+      HIPCHK(run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+      if (ly.bn)
+        HIPCHK(gw::launch_bn_apply_tanh(z, savedf(w.mean[l]), savedf(w.invstd[l]), m->params + ly.g,
+                                        m->params + ly.be, a, n, ly.co, lout[l], st));
+      Z[l] = z;
+      A[l] = a;
+      in = a;
+    }
+    return GW_OK;
+  };
+  const float* g = dnoise;
+  int gi = 0;
+  for (int l = L - 1; l >= 0; --l) {
+    if (rec) {
+      if (l == L - 1 && w.ckpt + 1 <= L - 2) CHK(recompute(w.ckpt + 1, L - 2, savedf(w.a[w.ckpt])));
+      if (l == w.ckpt) CHK(recompute(0, w.ckpt, x));
+    }
+    const LayerD& ly = m->layers[l];
+    const float* a_in = l == 0 ? x : A[l - 1];
+    const float* dz = g;
+    float* dzb = scf(b.dz);
+    if (ly.bn) {
+      HIPCHK(gw::launch_bn_tanh_backward(g, A[l], Z[l], savedf(w.mean[l]), savedf(w.invstd[l]),
+                                         m->params + ly.g, n, ly.co, lout[l], partial,
+                                         gw::red_chunks(n, lout[l]), dzb, dparams + ly.g,
+                                         dparams + ly.be, st));
+      HIPCHK(gw::launch_zero_floats(dparams + ly.m, 2 * ly.co, st));
+      dz = dzb;
+    }
+    HIPCHK(gw::launch_channel_sum(dz, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]),
+                                  dparams + ly.b, st));
+    if (ly.type == GW_LAYER_CONV)
+      HIPCHK(gw::launch_wgrad(dz, ly.co, lout[l], a_in, ly.ci, lin[l], n, ly.k, ly.s, ly.p, sc + b.wg,
+                              dparams + ly.w, st));
+    else
+      HIPCHK(gw::launch_wgrad(a_in, ly.ci, lin[l], dz, ly.co, lout[l], n, ly.k, ly.s, ly.p, sc + b.wg,
+                              dparams + ly.w, st));
+    if (l == 0) break;
+    // input gradient: the adjoint convolution with the same weights
+    gw::ConvP p{};
+    p.n = n;
+    p.Ci = ly.co;
+    p.Co = ly.ci;
+    p.Lin = lout[l];
+    p.Lout = lin[l];
+    p.k = ly.k;
+    p.stride = ly.s;
+    p.pad = ly.p;
+    p.w = m->params + ly.w;
+    p.x = dz;
+    p.bias = nullptr;
+    float* gout = scf(b.g[gi]);
+    gi ^= 1;
+    p.y = gout;
+    if (ly.type == GW_LAYER_CONV) {
+      p.wsi = (int64_t)ly.ci * ly.k;  // transposed kernel reads w[i*wsi + o*wso + j], i = conv out ch
+      p.wso = ly.k;
+      HIPCHK(gw::launch_conv_fp32(p, true, gw::EPI_BIAS, gw::SRC_DENSE, st));
+    } else {
+      p.wso = (int64_t)ly.co * ly.k;  // conv kernel reads w[o*wso + i*wsi + j], o = convT in ch
+      p.wsi = ly.k;
+      HIPCHK(gw::launch_conv_fp32(p, false, gw::EPI_BIAS, gw::SRC_DENSE, st));
+    }
+    g = gout;
+  }
+  return GW_OK;
+}
+
+// ===========================================================================
+// Band-passed MSE
+// ===========================================================================
+namespace {
+int band(int W, float fs, float f_lo, float f_hi, int* k_lo, int* k_hi) {
+  if (W < 2 || !(fs > 0) || !(f_lo >= 0) || !(f_hi >= f_lo)) return fail(GW_EINVAL, "bad band");
+  int lo = -1, hi = -2;
+  for (int k = 0; k <= W / 2; ++k) {
+    const double f = (double)k * (double)fs / (double)W;
+    if (f >= (double)f_lo && f <= (double)f_hi) {
+      if (lo < 0) lo = k;
+      hi = k;
+    }
+  }
+  if (lo < 0) return fail(GW_EINVAL, "no DFT bin inside the band");
+  *k_lo = lo;
+  *k_hi = hi;
+  return GW_OK;
+}
+}  // namespace
+
+extern "C" int gw_bandpass_workspace(int32_t n, int32_t W, float fs, float f_lo, float f_hi,
+                                     size_t* bytes) {
+  if (!bytes || n < 1) return fail(GW_EINVAL, "bad argument");
+  int lo, hi;
+  CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
+  *bytes = r256((size_t)n * (hi - lo + 1) * 2 * sizeof(float));
+  return GW_OK;
+}
+
+extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float f_hi,
+                               const float* strain, const float* noise, float* loss, float* dnoise,
+                               void* ws, size_t ws_bytes, void* hip_stream) {
+  if (n < 1 || !strain || !noise || !ws || (!loss && !dnoise)) return fail(GW_EINVAL, "bad argument");
+  int lo, hi;
+  CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
+  if (ws_bytes < (size_t)n * (hi - lo + 1) * 2 * sizeof(float)) return fail(GW_EINVAL, "workspace too small");
+  HIPCHK(gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ws), loss, dnoise,
+                             S(hip_stream)));
+  return GW_OK;
+}
+
+// ===========================================================================
+// BBHnet
+// ===========================================================================
+namespace {
+struct BbWs {
+  size_t gath = NONE, h = 0, o[2] = {0, 0}, total = 0;
+};
+int bb_layout(const gw_model* m, int n, int W, bool pool, int precision, BbWs& b) {
+  const int Sn = (int)m->stages.size();
+  if (W < 1 || W % (1 << Sn)) return fail(GW_EINVAL, "W must be a multiple of 2^stages");
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += r256(bytes);
+    return o;
+  };
+  (void)precision;
+  if (pool) b.gath = take((size_t)n * m->c_in * W * 4);
+  size_t mh = 256;
+  int L = W;
+  for (auto& sd : m->stages) {
+    L /= 2;
+    mh = std::max(mh, (size_t)n * sd.co * L * 4);
+  }
+  b.h = take(mh);
+  b.o[0] = take(mh);
+  b.o[1] = take(mh);
+  b.total = off;
+  return GW_OK;
+}
+}  // namespace
+
+extern "C" int bbhnet_workspace(const gw_model* m, int32_t n, int32_t W, int32_t precision,
+                                size_t* bytes) {
+  if (!m || !bytes) return fail(GW_EINVAL, "null argument");
+  if (m->kind != GW_MODEL_BBHNET) return fail(GW_ESTATE, "not a BBHnet model");
+  if (n < 1) return fail(GW_EINVAL, "n must be >= 1");
+  BbWs b;
+  CHK(bb_layout(m, n, W, true, precision, b));
+  *bytes = b.total;
+  return GW_OK;
+}
+
+extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x,
+                              int32_t n, int32_t W, float* logits, int32_t precision, void* ws,
+                              size_t ws_bytes, void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (m->kind != GW_MODEL_BBHNET) return fail(GW_ESTATE, "not a BBHnet model");
+  if (n == 0) return GW_OK;
+  if (n < 0) return fail(GW_EINVAL, "negative n");
+  if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
+  if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
+  if (!logits || !ws) return fail(GW_EINVAL, "null logits or workspace");
+  if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
+  if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
+  BbWs b;
+  CHK(bb_layout(m, n, W, pool != nullptr, precision, b));
+  if (ws_bytes < b.total) return fail(GW_EINVAL, "workspace too small: need " + std::to_string(b.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GW_EINVAL, "workspace not 256-byte aligned");
+  char* wsb = reinterpret_cast<char*>(ws);
+  const float* in = x;
+  if (pool) {
+    std::vector<Item> items(n);
+    std::vector<char> seen(pool->max_slots, 0);
+    for (int i = 0; i < n; ++i) {
+      CHK(pool->check_slot(slots[i]));
+      if (seen[slots[i]]) return fail(GW_EINVAL, "slot appears twice in one call");
+      seen[slots[i]] = 1;
+      const auto& s = pool->slots[slots[i]];
+      if (s.C != m->c_in || s.W != W) return fail(GW_EINVAL, "slot C/W does not match the model and W");
+      std::memset(&items[i], 0, sizeof(Item));
+      items[i].ring = pool->ring_elem(s);
+      items[i].shadow = pool->shadow_elem(s);
+      items[i].head = s.head;
+      items[i].C = s.C;
+      items[i].W = s.W;
+    }
+    const Item* dev = nullptr;
+    CHK(pool->stager.stage(items, st, &dev));
+    float* g = reinterpret_cast<float*>(wsb + b.gath);
+    HIPCHK(gw::launch_gather(pool->arena, dev, n, m->c_in, W, g, nullptr, st));
+    in = g;
+  }
+  int L = W;
+  const float* P = m->params;
+  for (size_t s = 0; s < m->stages.size(); ++s) {
+    const auto& sd = m->stages[s];
+    const int Lo = L / 2;
+    gw::ConvP pa{};
+    pa.n = n;
+    pa.Ci = sd.ci;
+    pa.Co = sd.co;
+    pa.Lin = L;
+    pa.Lout = Lo;
+    pa.k = 7;
+    pa.stride = 2;
+    pa.pad = 3;
+    pa.w = P + sd.wa;
+    pa.wso = (int64_t)sd.ci * 7;
+    pa.wsi = 7;
+    pa.bias = P + sd.ba;
+    pa.x = in;
+    pa.y = reinterpret_cast<float*>(wsb + b.h);
+    if (sd.bf16) pa.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wa_bf);
+    gw::ConvP pb{};
+    pb.n = n;
+    pb.Ci = sd.co;
+    pb.Co = sd.co;
+    pb.Lin = Lo;
+    pb.Lout = Lo;
+    pb.k = 7;
+    pb.stride = 1;
+    pb.pad = 3;
+    pb.w = P + sd.wb;
+    pb.wso = (int64_t)sd.co * 7;
+    pb.wsi = 7;
+    pb.bias = P + sd.bb;
+    pb.x = pa.y;
+    pb.xs = in;
+    pb.Cs = sd.ci;
+    pb.Ls = L;
+    pb.ws = P + sd.ws;
+    pb.bs = P + sd.bs;
+    pb.y = reinterpret_cast<float*>(wsb + b.o[s & 1]);
+    if (sd.bf16) pb.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wb_bf);
+    if (precision == GW_BF16) {
+      HIPCHK(gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
+      HIPCHK(gw::launch_conv_bf16(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
+    } else {
+      HIPCHK(gw::launch_conv_fp32(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
+      HIPCHK(gw::launch_conv_fp32(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
+    }
+    in = pb.y;
+    L = Lo;
+  }
+  HIPCHK(gw::launch_gap_linear(in, P + m->head_w, P + m->head_b, logits, n, m->c_last, L, st));
+  return GW_OK;
+}

@@ -1,0 +1,109 @@
+// Internal declarations shared by the ABI layer and the HIP kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace gw {
+
+// Per-item descriptor of a batched call, staged host->device once per call.
+// Offsets are in elements of the arena viewed as float (ring) or uint16 (shadow).
+struct Item {
+  int64_t ring;    // fp32 ring [C][W] of the slot
+  int64_t shadow;  // bf16 shadow [C][W] of the slot
+  int64_t src;     // snapshot_update: offset of the [C][s] block in `samples`
+  int64_t out;     // forward: offset of this item's [s] block in strain/clean
+  int32_t head;    // ring index of the oldest sample (update: before writing)
+  int32_t s;       // new samples per request (stride)
+  int32_t C, W;
+};
+static_assert(sizeof(Item) == 48, "Item layout");
+
+enum Epi : int {
+  EPI_AFFINE = 0,       // y = acc*scale[o] + shift[o]
+  EPI_AFFINE_TANH = 1,  // y = tanh(acc*scale[o] + shift[o])
+  EPI_BIAS = 2,         // y = acc + bias[o]   (bias may be null)
+  EPI_RELU = 3,         // y = max(acc + bias[o], 0)
+  EPI_RESID_RELU = 4,   // y = max(acc + bias[o] + shortcut(x_stage)[o], 0)
+  EPI_OUT = 5,          // y = acc*scale + shift; noise + causal clean outputs
+};
+
+enum Src : int { SRC_DENSE = 0, SRC_RING = 1 };
+
+// One convolution layer launch (direct FP32 or BF16 MFMA).
+struct ConvP {
+  // input
+  const float* x;          // dense fp32 [n][Ci][Lin] (SRC_DENSE)
+  const uint16_t* xh;      // dense bf16 [n][Ci][Lin] (BF16 kernels, SRC_DENSE)
+  const void* arena;       // pool arena base (SRC_RING)
+  const Item* items;       // per-item descriptors (SRC_RING or EPI_OUT)
+  // output
+  float* y;                // fp32 [n][Co][Lout]
+  uint16_t* yh;            // bf16 [n][Co][Lout] (BF16 kernels, intermediate layers)
+  // weights: w[o*wso + i*wsi + j] for conv, w[i*wsi + o*wso + j] for transposed
+  const float* w;
+  int64_t wso, wsi;
+  const uint16_t* wpk;     // packed bf16 weights (BF16 kernels)
+  const float* bias;
+  const float* scale;
+  const float* shift;
+  // residual shortcut (EPI_RESID_RELU): 1x1 stride-2 conv of the stage input
+  const float* xs;         // stage input fp32 [n][Cs][Ls]
+  const uint16_t* xsh;     // stage input bf16
+  const float* ws;         // [Co][Cs]
+  const float* bs;         // [Co]
+  int Cs, Ls;
+  // outputs of EPI_OUT
+  float* noise;            // [n][W] or null
+  const float* strain;     // packed, or null
+  float* clean;            // packed, or null
+  // shape
+  int n, Ci, Co, Lin, Lout, k, stride, pad;
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
+hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
+bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool transposed);
+size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
+hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool transposed,
+                            hipStream_t st);
+
+hipError_t launch_snapshot(void* arena, const Item* items, int n, int max_cs, const float* samples,
+                           hipStream_t st);
+hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_zero_floats(float* dst, int64_t n, hipStream_t st);
+// Window fetch: logical window [C][W] of each item's ring into dense [n][C][W].
+hipError_t launch_gather(const void* arena, const Item* items, int n, int C, int W, float* out,
+                         uint16_t* outh, hipStream_t st);
+
+hipError_t launch_fold_bn(const float* b, const float* gamma, const float* beta, const float* mean,
+                          const float* var, float* scale, float* shift, int C, hipStream_t st);
+
+hipError_t launch_gap_linear(const float* a, const float* w, const float* b, float* logits, int n,
+                             int C, int L, hipStream_t st);
+
+// Training
+int red_chunks(int n, int L);  // chunks of a per-channel (batch, time) reduction
+hipError_t launch_bn_stats(const float* z, int n, int C, int L, double* partial, int nchunk,
+                           float* mean, float* invstd, hipStream_t st);
+hipError_t launch_bn_apply_tanh(const float* z, const float* mean, const float* invstd,
+                                const float* gamma, const float* beta, float* a, int n, int C,
+                                int L, hipStream_t st);
+hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* z,
+                                   const float* mean, const float* invstd, const float* gamma,
+                                   int n, int C, int L, double* partial, int nchunk, float* dz,
+                                   float* dgamma, float* dbeta, hipStream_t st);
+hipError_t launch_channel_sum(const float* x, int n, int C, int L, double* partial, int nchunk,
+                              float* out, hipStream_t st);
+int wgrad_chunks(int n, int Lp);
+size_t wgrad_scratch_bytes(int n, int Lp, int nw);
+// LDS per block: 4*(Ca*64 + Cc*(stride*63 + k)) bytes, must be <= 64 KiB.
+hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, int Lq, int n,
+                        int k, int stride, int pad, void* scratch, float* dw, hipStream_t st);
+hipError_t launch_bandpass(int n, int W, int k_lo, int k_hi, const float* strain,
+                           const float* noise, float* proj, float* loss, float* dnoise,
+                           hipStream_t st);
+
+}  // namespace gw

@@ -1,0 +1,131 @@
+"""GPU parity of the DeepClean training step (batch-statistics forward,
+band-passed MSE, hand-written backward) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2108_12430_amd import gwstream as gs
+from paper_2108_12430_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, r):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - r)) / np.max(np.abs(r)))
+
+
+def tensor_slices(layers):
+    """(name, start, stop) of every parameter tensor in the flat vector."""
+    out, off = [], 0
+    for l, (typ, ci, co, k, s, p, op, bn) in enumerate(layers):
+        for name, n in [("w", ci * co * k), ("b", co)] + ([("gamma", co), ("beta", co), ("mean", co),
+                                                             ("var", co)] if bn else []):
+            out.append((f"L{l}.{name}", off, off + n))
+            off += n
+    return out
+
+
+def grad_errors(got, exp, layers):
+    """Per-tensor normwise error.  The bias of a conv followed by batch
+    normalisation has an exactly zero gradient (the batch mean removes it), so
+    its error is measured against the largest gradient of the layer's weight."""
+    errs = {}
+    sl = tensor_slices(layers)
+    for name, a, b in sl:
+        if name.endswith(".mean") or name.endswith(".var"):
+            assert np.all(got[a:b] == 0)
+            continue
+        r = exp[a:b]
+        scale = np.max(np.abs(r))
+        lname = name.split(".")[0]
+        if name.endswith(".b") and layers[int(lname[1:])][7]:
+            wa, wb = [(x, y) for nm, x, y in sl if nm == lname + ".w"][0]
+            scale = np.max(np.abs(exp[wa:wb]))
+        errs[name] = float(np.max(np.abs(got[a:b] - r)) / scale)
+    return errs
+
+
+def test_bandpass_loss_and_grad():
+    n, W = 4, 32768
+    strain = synth.gaussian(50, (n, W))
+    t = np.arange(W) / 4096.0
+    strain = (strain + 2 * np.sin(2 * np.pi * 60.3 * t)).astype(np.float32)
+    noise = synth.gaussian(51, (n, W), 0.5)
+    loss, dn = gs.bandpass_mse(torch.from_numpy(strain).to(DEV), torch.from_numpy(noise).to(DEV))
+    el, edn = ref.bandpass_mse(strain, noise, 4096.0, 55.0, 65.0)
+    assert abs(loss.item() - el) <= 1e-5 * abs(el)
+    assert rel(dn.cpu().numpy(), edn) <= 1e-5
+
+
+def _train_step(m, x, strain, flags, fs=4096.0, lossfn="bandpass"):
+    n, W = x.shape[0], x.shape[-1]
+    xt = torch.from_numpy(x).to(DEV)
+    st = torch.from_numpy(strain).to(DEV)
+    noise = torch.empty((n, W), device=DEV)
+    ws = m.forward(x=xt, noise=noise, flags=flags)
+    if lossfn == "bandpass":
+        loss, dn = gs.bandpass_mse(st, noise, fs, 55.0, 65.0)
+    else:
+        dn = (-2.0 / (n * W)) * (st - noise)
+    dp = torch.empty_like(m.params)
+    m.backward(xt, dn.contiguous(), ws, dp, flags=flags)
+    torch.cuda.synchronize()
+    return noise.cpu().numpy(), dp.cpu().numpy()
+
+
+@pytest.mark.parametrize("lossfn", ["bandpass", "mse"])
+def test_grad_tiny_instance(lossfn):
+    """Two-layer, four-channel, 256-sample instance: GPU gradient vs the
+    oracle gradient (which is itself pinned by finite differences)."""
+    layers = synth.tiny_layers()
+    params = synth.deepclean_params(5, layers)
+    m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
+    x = synth.gaussian(5, (2, 4, 256))
+    t = np.arange(256) / 4096.0
+    strain = (synth.gaussian(6, (2, 256)) + 3 * np.sin(2 * np.pi * 64 * t)).astype(np.float32)
+    noise, g = _train_step(m, x, strain, gs.TRAIN, lossfn=lossfn)
+    en = ref.deepclean_forward(params, x, layers, train=True)
+    assert rel(noise, en) <= 1e-5
+    if lossfn == "bandpass":
+        _, dn = ref.bandpass_mse(strain, en, 4096.0, 55.0, 65.0)
+    else:
+        _, dn = ref.mse(strain, en)
+    eg = ref.deepclean_grad(params, x, dn, layers)
+    errs = grad_errors(g, eg, layers)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_grad_full_window():
+    """8-s windows (21 x 32768) through the full network, batch 4, band-passed
+    loss: per-tensor error of every gradient against the oracle."""
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
+    wit, strain = synth.witness_stream(4, 4 * 32768)
+    x = np.ascontiguousarray(wit.reshape(21, 4, 32768).transpose(1, 0, 2))
+    sb = np.ascontiguousarray(strain.reshape(4, 32768))
+    noise, g = _train_step(m, x, sb, gs.TRAIN)
+    en = ref.deepclean_forward(params, x, layers, train=True)
+    assert rel(noise, en) <= 1e-5
+    _, dn = ref.bandpass_mse(sb, en, 4096.0, 55.0, 65.0)
+    eg = ref.deepclean_grad(params, x, dn, layers)
+    errs = grad_errors(g, eg, layers)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_recompute_bitwise():
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
+    x = synth.gaussian(60, (2, 21, 8192))
+    strain = synth.gaussian(61, (2, 8192))
+    n0, g0 = _train_step(m, x, strain, gs.TRAIN)
+    n1, g1 = _train_step(m, x, strain, gs.TRAIN | gs.RECOMPUTE)
+    assert np.array_equal(n0, n1)
+    assert np.array_equal(g0, g1)
+    assert m.workspace_bytes(2, 8192, gs.FP32, gs.TRAIN | gs.RECOMPUTE) < m.workspace_bytes(2, 8192, gs.FP32,
+                                                                                             gs.TRAIN)
+    n2, g2 = _train_step(m, x, strain, gs.TRAIN)
+    assert np.array_equal(g0, g2)   # deterministic across runs
