@@ -1,0 +1,348 @@
+#!/usr/bin/env python3
+"""Streaming-inference benchmark on one MI355X.
+
+Workload: the multi-stream serving mix run closed-loop (every stream always
+has its next request pending): 179 DeepClean streams (21 witness channels,
+8-s windows of 32768 samples at 4096 Hz) and 77 BBHnet streams (2 detectors,
+1-s windows of 2048 samples at 2048 Hz); each stream's request carries 1/16,
+1/8 or 1/4 s of new samples (seeded per stream).  One step = one request of
+every stream: ingest of the staged samples into the snapshot rings (one
+batched snapshot_update), the DeepClean forward of all 179 windows with the
+causal slice and noise subtraction, and the BBHnet forward of all 77
+windows.  Inputs for every timed step are resident in HBM before timing.
+
+Reported: streamed samples/s (sum of new samples over completed requests per
+second, the BF16 batched path), per-update latency p50/p99 (request ready ->
+result complete, synchronous pass), the same workload on the FP32 plain path
+(one stream at a time, FP32 direct convolution), the dominant kernel's
+roofline figures from HIP events, and the FP64 CPU oracle on a bounded sample
+of the same requests.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "streamed samples/sec + p99 per-update latency, BF16 batched vs FP32 plain"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+N_DC, N_BB = 179, 77
+DC_C, DC_W, DC_FS = 21, 32768, 4096
+BB_C, BB_W, BB_FS = 2, 2048, 2048
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_mix(seed=6):
+    rng = np.random.default_rng(seed)
+    frac = np.array([1 / 16, 1 / 8, 1 / 4])
+    dc_s = (rng.choice(frac, N_DC) * DC_FS).astype(np.int64)
+    bb_s = (rng.choice(frac, N_BB) * BB_FS).astype(np.int64)
+    return dc_s, bb_s
+
+
+def layer_shapes(layers, W):
+    out, L = [], W
+    for (typ, ci, co, k, s, p, op, bn) in layers:
+        Lo = (L + 2 * p - k) // s + 1 if typ == "conv" else (L - 1) * s - 2 * p + k + op
+        out.append((typ, ci, co, k, L, Lo))
+        L = Lo
+    return out
+
+
+def algorithmic(name, precision, layers, dc_s, bb_s):
+    """(flops, bytes) per launch of a named kernel in one step."""
+    esz = 2 if precision == "bf16" else 4
+    kind, _, tag = name.partition(".")
+    if kind.startswith("dc_conv"):
+        l = int(tag[1:])
+        typ, ci, co, k, Li, Lo = layer_shapes(layers, DC_W)[l]
+        n = N_DC
+        macs = n * co * Lo * ci * k if typ == "conv" else n * ci * Li * co * k
+        by = n * ci * Li * esz + co * ci * k * esz
+        if l == len(layers) - 1:
+            by += 2 * 4 * int(dc_s.sum())          # strain in, clean out
+        else:
+            by += n * co * Lo * esz
+        return 2.0 * macs, float(by)
+    if kind.startswith("bbh_conv"):
+        st = int(tag[1:])
+        n, L = N_BB, BB_W
+        chans = [(2, 32), (32, 64), (64, 128)]
+        for i in range(st):
+            L //= 2
+        ci, co = chans[st]
+        Lo = L // 2
+        if "conva" in kind:
+            macs = n * co * Lo * ci * 7
+            by = n * ci * L * esz + n * co * Lo * esz + co * ci * 7 * esz
+        else:
+            macs = n * co * Lo * co * 7 + n * co * Lo * ci
+            by = n * co * Lo * esz * 2 + n * ci * L * esz + co * co * 7 * esz
+        return 2.0 * macs, float(by)
+    if kind == "snapshot":
+        cs = DC_C * int(dc_s.sum()) + BB_C * int(bb_s.sum())
+        return 0.0, float(cs * (4 + 4 + 2))
+    if kind == "gather":
+        return 0.0, float(N_BB * BB_C * BB_W * 8)
+    return 0.0, 0.0
+
+
+def cpu_baseline(dc_s, bb_s, budget_s=12.0):
+    """The FP64 oracle on a bounded sample of the same requests: each request
+    recomputes its stream's full window (plain definition), then the causal
+    slice and subtraction for DeepClean streams."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import ref
+    from paper_2108_12430_amd import synth
+    dcp = synth.deepclean_params(0)
+    bbp = synth.bbhnet_params(0)
+    wit, strain = synth.witness_stream(11, DC_W + 1024)
+    bbx = synth.gaussian(12, (BB_C, BB_W + 512))
+    samples = 0
+    n_dc = n_bb = 0
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < budget_s or n_dc == 0 or n_bb == 0:
+        if (i + 1) * N_DC // (N_DC + N_BB) > i * N_DC // (N_DC + N_BB):   # interleave 179:77
+            s = int(dc_s[n_dc % N_DC])
+            x = ref.snapshot_after(wit, DC_W + s, DC_W)[None]
+            noise = ref.deepclean_forward(dcp, x)
+            ref.causal_clean(noise, strain[None, DC_W: DC_W + s])
+            n_dc += 1
+        else:
+            s = int(bb_s[n_bb % N_BB])
+            x = ref.snapshot_after(bbx, BB_W + s, BB_W)[None]
+            ref.bbhnet_forward(bbp, x)
+            n_bb += 1
+        samples += s
+        i += 1
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": samples / dt, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_dc} DeepClean + {n_bb} BBHnet requests of the same mix (FP64 numpy oracle, "
+                      f"full-window recompute per request), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--lat-steps", type=int, default=60)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2108_12430_amd import gwstream as gs
+    from paper_2108_12430_amd import synth
+
+    dev = torch.device("cuda:0")
+    dc_s, bb_s = make_mix()
+    layers = synth.deepclean_layers()
+    stages = synth.bbhnet_stages()
+    dc = gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(dev), layers)
+    bb = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(dev), stages)
+    prec = gs.BF16 if args.precision == "bf16" else gs.FP32
+    try:
+        dc.workspace_bytes(1, DC_W, prec)
+        probe = torch.zeros((1, DC_C, 64), device=dev)
+        dc.forward(x=probe, noise=torch.empty((1, 64), device=dev), precision=prec)
+    except gs.GwError as e:
+        if e.code != gs.GW_EUNSUPPORTED:
+            raise
+        log(f"bench: {args.precision} path unavailable ({e}); measuring fp32")
+        args.precision, prec = "fp32", gs.FP32
+
+    # pool with every stream admitted
+    ring = lambda c, w: ((c * w * 4 + 255) // 256 + (c * w * 2 + 255) // 256) * 256
+    arena = N_DC * ring(DC_C, DC_W) + N_BB * ring(BB_C, BB_W) + (64 << 20)
+    pool = gs.Pool(arena, max_slots=N_DC + N_BB, max_items=N_DC + N_BB)
+    dc_slots = [pool.open(DC_C, DC_W) for _ in range(N_DC)]
+    bb_slots = [pool.open(BB_C, BB_W) for _ in range(N_BB)]
+    slots = dc_slots + bb_slots
+    strides = np.concatenate([dc_s, bb_s])
+    offsets = np.zeros(len(slots), np.int64)
+    o = 0
+    for i, s in enumerate(strides):
+        offsets[i] = o
+        o += (DC_C if i < N_DC else BB_C) * int(s)
+    per_step_floats = o
+    dc_strain_len = int(dc_s.sum())
+    step_samples = int(strides.sum())
+    log(f"bench: {len(slots)} streams admitted, {step_samples} new samples per step, precision {args.precision}")
+
+    # synthetic sources (coloured-noise witnesses with mains lines; whitened detector noise)
+    nsrc = 1 << 20
+    wit, strain = synth.witness_stream(2, nsrc)
+    wit_t = torch.from_numpy(wit).to(dev)
+    strain_t = torch.from_numpy(strain).to(dev)
+    bbx_t = torch.from_numpy(synth.gaussian(3, (BB_C, nsrc))).to(dev)
+    n_steps_total = args.warmup + args.steps + args.lat_steps + 4
+    pos = (np.arange(len(slots)) * 104729) % (nsrc // 2)
+    staged, staged_strain = [], []
+    for k in range(n_steps_total):
+        blocks, sblocks = [], []
+        for i, s in enumerate(strides):
+            p = int(pos[i]) % (nsrc - 2048)
+            if i < N_DC:
+                blocks.append(wit_t[:, p:p + s].reshape(-1))
+                sblocks.append(strain_t[p:p + s])
+            else:
+                blocks.append(bbx_t[:, p:p + s].reshape(-1))
+            pos[i] += s
+        staged.append(torch.cat(blocks).contiguous())
+        staged_strain.append(torch.cat(sblocks).contiguous())
+    assert staged[0].numel() == per_step_floats
+    clean = torch.empty(dc_strain_len, device=dev)
+    logits = torch.empty(N_BB, device=dev)
+    ws_dc = torch.empty(dc.workspace_bytes(N_DC, DC_W, prec), dtype=torch.uint8, device=dev)
+    ws_bb = torch.empty(bb.workspace_bytes(N_BB, BB_W, prec), dtype=torch.uint8, device=dev)
+    dc_sl = np.array(dc_slots, np.int32)
+    bb_sl = np.array(bb_slots, np.int32)
+    torch.cuda.synchronize()
+    log(f"bench: staged {n_steps_total} steps of inputs in HBM")
+
+    def step(k):
+        pool.update(slots, strides, staged[k], offsets)
+        dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
+                   precision=prec, ws=ws_dc)
+        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb)
+
+    k = 0
+    for _ in range(args.warmup):
+        step(k)
+        k += 1
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(k)
+        k += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = step_samples * args.steps / dt
+    log(f"bench: {ms_per_step:.3f} ms/step, {value:.4g} samples/s")
+
+    # latency: each request is ready when its step is issued and complete when
+    # the step's work has finished (synchronous pass)
+    lat = []
+    for _ in range(args.lat_steps):
+        t1 = time.perf_counter()
+        step(k)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t1))
+        k += 1
+    lat = np.array(lat)
+    log(f"bench: latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    roof = None
+    if not args.no_roofline:
+        gs.profile_begin()
+        kp = 0
+        for _ in range(5):
+            step(kp % n_steps_total)
+            kp += 1
+        prof = gs.profile_end()
+        name, (cnt, tot) = max(prof.items(), key=lambda kv: kv[1][1])
+        avg_s = tot / cnt / 1e3
+        flops, by = algorithmic(name, args.precision, layers, dc_s, bb_s)
+        if args.precision == "fp32":
+            roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s"}
+        elif flops / max(by, 1.0) > BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+            roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": BF16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = name
+        roof["avg_us"] = avg_s * 1e6
+        roof["algorithmic_flops"] = flops
+        roof["algorithmic_bytes"] = by
+        step_ms = sum(v[1] for v in prof.values()) / 5
+        roof["kernels_ms_per_step"] = {k2: round(v[1] / 5, 4) for k2, v in sorted(prof.items())}
+        log(f"bench: dominant kernel {name} avg {avg_s * 1e6:.1f} us; kernel sum {step_ms:.3f} ms/step")
+
+    plain = None
+    if not args.no_plain:
+        ws1 = torch.empty(dc.workspace_bytes(1, DC_W, gs.FP32), dtype=torch.uint8, device=dev)
+        wsb1 = torch.empty(bb.workspace_bytes(1, BB_W, gs.FP32), dtype=torch.uint8, device=dev)
+        lat_plain, times = [], []
+        for _ in range(args.plain_steps):
+            kk = k % n_steps_total
+            ev0 = torch.cuda.Event(enable_timing=True)
+            evs = []
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ev0.record()
+            for i, sl in enumerate(slots):
+                pool.update([sl], [strides[i]], staged[kk], [offsets[i]])
+                if i < N_DC:
+                    so = int(dc_s[:i].sum())
+                    dc.forward(pool=pool, slots=[sl], W=DC_W, strides=[dc_s[i]],
+                               strain=staged_strain[kk][so:so + int(dc_s[i])], clean=clean[so:so + int(dc_s[i])],
+                               precision=gs.FP32, ws=ws1)
+                else:
+                    bb.forward(pool=pool, slots=[sl], W=BB_W, logits=logits[i - N_DC:i - N_DC + 1],
+                               precision=gs.FP32, ws=wsb1)
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                evs.append(e)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            lat_plain += [ev0.elapsed_time(e) for e in evs]
+            k += 1
+        tp = float(np.mean(times))
+        plain = {"value": step_samples / tp, "unit": "samples/s", "ms_per_step": 1e3 * tp,
+                 "p50_ms": float(np.percentile(lat_plain, 50)), "p99_ms": float(np.percentile(lat_plain, 99)),
+                 "dtype": "f32", "batching": "one stream per launch"}
+        log(f"bench: fp32 plain {plain['value']:.4g} samples/s, p99 {plain['p99_ms']:.3f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(dc_s, bb_s)
+        log(f"bench: cpu oracle {cpu['value']:.4g} samples/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision if args.precision == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "closed-loop serving mix: 179 DeepClean streams (21 ch x 32768, 4096 Hz) + "
+                               "77 BBHnet streams (2 ch x 2048, 2048 Hz), strides 1/16-1/4 s",
+                   "streams": N_DC + N_BB, "samples_per_step": step_samples,
+                   "channel_samples_per_step": int(DC_C * dc_s.sum() + BB_C * bb_s.sum())},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "fp32_plain": plain, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

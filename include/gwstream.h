@@ -244,6 +244,19 @@ int bbhnet_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, c
                    int32_t n, int32_t W, float* logits, int32_t precision, void* ws,
                    size_t ws_bytes, void* hip_stream);
 
+/* ---- measurement ------------------------------------------------------ */
+/*
+ * Kernel timing for benchmarks.  Between gw_profile_begin and gw_profile_end
+ * every kernel launch the library makes is bracketed by two HIP events
+ * recorded on the stream it is launched on.  gw_profile_end waits for those
+ * events and writes one line per launch name, "name count total_ms\n", into
+ * buf (NUL-terminated, truncated to len bytes), then stops recording.  Names
+ * are "<kernel>.<layer>", e.g. "dc_conv_fp32.L3".  Process-wide; not for use
+ * while another thread makes library calls.
+ */
+int gw_profile_begin(void);
+int gw_profile_end(char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,7 +81,81 @@ struct Stager {
   }
 };
 
+// Optional per-launch timing with HIP events recorded on the launch stream.
+struct Prof {
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> spare;
+  hipEvent_t get() {
+    if (!spare.empty()) {
+      hipEvent_t e = spare.back();
+      spare.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Prof g_prof;
+
 }  // namespace
+
+// Launch through a gw::launch_* function; with profiling on, bracket it with
+// events on the same stream.
+#define LAUNCH(name, st, expr)                                   \
+  do {                                                           \
+    hipEvent_t a_ = nullptr;                                     \
+    if (g_prof.on && (a_ = g_prof.get())) (void)hipEventRecord(a_, st); \
+    HIPCHK(expr);                                                \
+    if (a_) {                                                    \
+      hipEvent_t b_ = g_prof.get();                              \
+      if (b_) {                                                  \
+        (void)hipEventRecord(b_, st);                            \
+        g_prof.recs.push_back({std::string(name), a_, b_});      \
+      }                                                          \
+    }                                                            \
+  } while (0)
+
+static std::string nm(const char* k, const char* tag, int i) {
+  return std::string(k) + "." + tag + std::to_string(i);
+}
+
+extern "C" int gw_profile_begin(void) {
+  for (auto& r : g_prof.recs) {
+    g_prof.spare.push_back(r.a);
+    g_prof.spare.push_back(r.b);
+  }
+  g_prof.recs.clear();
+  g_prof.on = true;
+  return GW_OK;
+}
+
+extern "C" int gw_profile_end(char* buf, size_t len) {
+  g_prof.on = false;
+  std::map<std::string, std::pair<int, double>> agg;
+  for (auto& r : g_prof.recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& e = agg[r.name];
+    e.first += 1;
+    e.second += ms;
+  }
+  std::string out;
+  for (auto& kv : agg)
+    out += kv.first + " " + std::to_string(kv.second.first) + " " + std::to_string(kv.second.second) + "\n";
+  if (buf && len) {
+    const size_t n = std::min(len - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return GW_OK;
+}
 
 // ===========================================================================
 // Pool
@@ -246,7 +320,7 @@ extern "C" int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_
   items[0].W = s.W;
   const Item* dev = nullptr;
   CHK(pool->stager.stage(items, S(hip_stream), &dev));
-  HIPCHK(gw::launch_gather(pool->arena, dev, 1, s.C, s.W, out, out_bf16, S(hip_stream)));
+  LAUNCH("gather", S(hip_stream), gw::launch_gather(pool->arena, dev, 1, s.C, s.W, out, out_bf16, S(hip_stream)));
   return GW_OK;
 }
 
@@ -288,7 +362,7 @@ extern "C" int snapshot_update(gw_pool* pool, int32_t n, const int32_t* slots, c
   }
   const Item* dev = nullptr;
   CHK(pool->stager.stage(items, S(hip_stream), &dev));
-  HIPCHK(gw::launch_snapshot(pool->arena, dev, n, max_cs, samples, S(hip_stream)));
+  LAUNCH("snapshot", S(hip_stream), gw::launch_snapshot(pool->arena, dev, n, max_cs, samples, S(hip_stream)));
   for (int i = 0; i < n; ++i) {
     auto& s = pool->slots[slots[i]];
     s.head = (s.head + strides[i]) % s.W;
@@ -764,7 +838,8 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
         p.yh = reinterpret_cast<uint16_t*>(wsb + w.buf[l & 1]);
       }
       if (precision == GW_BF16 && l > 0) p.xh = reinterpret_cast<const uint16_t*>(in);
-      HIPCHK(run_conv(p, ly, epi, src, precision, st));
+      LAUNCH(nm(precision == GW_BF16 ? "dc_conv_bf16" : "dc_conv_fp32", "L", l), st,
+             run_conv(p, ly, epi, src, precision, st));
       in = p.y;
     }
     return GW_OK;
@@ -781,7 +856,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       p.noise = noise;
       p.clean = clean;
       p.strain = strain;
-      HIPCHK(run_conv(p, ly, gw::EPI_OUT, gw::SRC_DENSE, GW_FP32, st));
+      LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_OUT, gw::SRC_DENSE, GW_FP32, st));
       break;
     }
     float* z = reinterpret_cast<float*>(wsb + (w.ckpt >= 0 ? w.ztmp : (ly.bn ? w.z[l] : w.a[l])));
@@ -794,12 +869,14 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       a = reinterpret_cast<float*>(wsb + w.atmp[l & 1]);
     if (!ly.bn) z = a;
     p.y = z;
-    HIPCHK(run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+    LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
     if (ly.bn) {
       float* mean = reinterpret_cast<float*>(wsb + w.mean[l]);
       float* invstd = reinterpret_cast<float*>(wsb + w.invstd[l]);
-      HIPCHK(gw::launch_bn_stats(z, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]), mean, invstd, st));
-      HIPCHK(gw::launch_bn_apply_tanh(z, mean, invstd, m->params + ly.g, m->params + ly.be, a, n, ly.co,
+      LAUNCH(nm("bn_stats", "L", l), st,
+             gw::launch_bn_stats(z, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]), mean, invstd, st));
+      LAUNCH(nm("bn_apply", "L", l), st,
+             gw::launch_bn_apply_tanh(z, mean, invstd, m->params + ly.g, m->params + ly.be, a, n, ly.co,
                                       lout[l], st));
     }
     in = a;
@@ -933,9 +1010,9 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
       float* a = scf(b.a[l]);
       float* z = ly.bn ? scf(b.z[l]) : a;
       p.y = z;
-      HIPCHK(run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+      LAUNCH(nm("dc_recompute_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
       if (ly.bn)
-        HIPCHK(gw::launch_bn_apply_tanh(z, savedf(w.mean[l]), savedf(w.invstd[l]), m->params + ly.g,
+        LAUNCH(nm("bn_apply", "L", l), st, gw::launch_bn_apply_tanh(z, savedf(w.mean[l]), savedf(w.invstd[l]), m->params + ly.g,
                                         m->params + ly.be, a, n, ly.co, lout[l], st));
       Z[l] = z;
       A[l] = a;
@@ -955,20 +1032,20 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
     const float* dz = g;
     float* dzb = scf(b.dz);
     if (ly.bn) {
-      HIPCHK(gw::launch_bn_tanh_backward(g, A[l], Z[l], savedf(w.mean[l]), savedf(w.invstd[l]),
+      LAUNCH(nm("bn_bwd", "L", l), st, gw::launch_bn_tanh_backward(g, A[l], Z[l], savedf(w.mean[l]), savedf(w.invstd[l]),
                                          m->params + ly.g, n, ly.co, lout[l], partial,
                                          gw::red_chunks(n, lout[l]), dzb, dparams + ly.g,
                                          dparams + ly.be, st));
-      HIPCHK(gw::launch_zero_floats(dparams + ly.m, 2 * ly.co, st));
+      LAUNCH("zero", st, gw::launch_zero_floats(dparams + ly.m, 2 * ly.co, st));
       dz = dzb;
     }
-    HIPCHK(gw::launch_channel_sum(dz, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]),
+    LAUNCH(nm("bias_grad", "L", l), st, gw::launch_channel_sum(dz, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]),
                                   dparams + ly.b, st));
     if (ly.type == GW_LAYER_CONV)
-      HIPCHK(gw::launch_wgrad(dz, ly.co, lout[l], a_in, ly.ci, lin[l], n, ly.k, ly.s, ly.p, sc + b.wg,
+      LAUNCH(nm("wgrad", "L", l), st, gw::launch_wgrad(dz, ly.co, lout[l], a_in, ly.ci, lin[l], n, ly.k, ly.s, ly.p, sc + b.wg,
                               dparams + ly.w, st));
     else
-      HIPCHK(gw::launch_wgrad(a_in, ly.ci, lin[l], dz, ly.co, lout[l], n, ly.k, ly.s, ly.p, sc + b.wg,
+      LAUNCH(nm("wgrad", "L", l), st, gw::launch_wgrad(a_in, ly.ci, lin[l], dz, ly.co, lout[l], n, ly.k, ly.s, ly.p, sc + b.wg,
                               dparams + ly.w, st));
     if (l == 0) break;
     // input gradient: the adjoint convolution with the same weights
@@ -990,11 +1067,11 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
     if (ly.type == GW_LAYER_CONV) {
       p.wsi = (int64_t)ly.ci * ly.k;  // transposed kernel reads w[i*wsi + o*wso + j], i = conv out ch
       p.wso = ly.k;
-      HIPCHK(gw::launch_conv_fp32(p, true, gw::EPI_BIAS, gw::SRC_DENSE, st));
+      LAUNCH(nm("dgrad", "L", l), st, gw::launch_conv_fp32(p, true, gw::EPI_BIAS, gw::SRC_DENSE, st));
     } else {
       p.wso = (int64_t)ly.co * ly.k;  // conv kernel reads w[o*wso + i*wsi + j], o = convT in ch
       p.wsi = ly.k;
-      HIPCHK(gw::launch_conv_fp32(p, false, gw::EPI_BIAS, gw::SRC_DENSE, st));
+      LAUNCH(nm("dgrad", "L", l), st, gw::launch_conv_fp32(p, false, gw::EPI_BIAS, gw::SRC_DENSE, st));
     }
     g = gout;
   }
@@ -1038,7 +1115,7 @@ extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float
   int lo, hi;
   CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
   if (ws_bytes < (size_t)n * (hi - lo + 1) * 2 * sizeof(float)) return fail(GW_EINVAL, "workspace too small");
-  HIPCHK(gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ws), loss, dnoise,
+  LAUNCH("bandpass", S(hip_stream), gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ws), loss, dnoise,
                              S(hip_stream)));
   return GW_OK;
 }
@@ -1124,14 +1201,18 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     const Item* dev = nullptr;
     CHK(pool->stager.stage(items, st, &dev));
     float* g = reinterpret_cast<float*>(wsb + b.gath);
-    HIPCHK(gw::launch_gather(pool->arena, dev, n, m->c_in, W, g, nullptr, st));
+    LAUNCH("gather", st, gw::launch_gather(pool->arena, dev, n, m->c_in, W, g, nullptr, st));
     in = g;
   }
   int L = W;
   const float* P = m->params;
-  for (size_t s = 0; s < m->stages.size(); ++s) {
+  const bool bf = precision == GW_BF16;
+  const int Sn = (int)m->stages.size();
+  const void* cur = in;  // stage input: fp32 for stage 0, bf16 after (BF16 path)
+  for (int s = 0; s < Sn; ++s) {
     const auto& sd = m->stages[s];
     const int Lo = L / 2;
+    const bool last = s == Sn - 1;
     gw::ConvP pa{};
     pa.n = n;
     pa.Ci = sd.ci;
@@ -1145,9 +1226,6 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     pa.wso = (int64_t)sd.ci * 7;
     pa.wsi = 7;
     pa.bias = P + sd.ba;
-    pa.x = in;
-    pa.y = reinterpret_cast<float*>(wsb + b.h);
-    if (sd.bf16) pa.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wa_bf);
     gw::ConvP pb{};
     pb.n = n;
     pb.Ci = sd.co;
@@ -1161,24 +1239,45 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     pb.wso = (int64_t)sd.co * 7;
     pb.wsi = 7;
     pb.bias = P + sd.bb;
-    pb.x = pa.y;
-    pb.xs = in;
     pb.Cs = sd.ci;
     pb.Ls = L;
     pb.ws = P + sd.ws;
     pb.bs = P + sd.bs;
-    pb.y = reinterpret_cast<float*>(wsb + b.o[s & 1]);
-    if (sd.bf16) pb.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wb_bf);
-    if (precision == GW_BF16) {
-      HIPCHK(gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
-      HIPCHK(gw::launch_conv_bf16(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
+    void* hbuf = wsb + b.h;
+    void* obuf = wsb + b.o[s & 1];
+    if (bf) {
+      pa.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wa_bf);
+      pb.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wb_bf);
+      if (s == 0) {
+        pa.x = reinterpret_cast<const float*>(cur);
+        pb.xs = reinterpret_cast<const float*>(cur);
+      } else {
+        pa.xh = reinterpret_cast<const uint16_t*>(cur);
+        pb.xsh = reinterpret_cast<const uint16_t*>(cur);
+      }
+      pa.yh = reinterpret_cast<uint16_t*>(hbuf);
+      pb.xh = pa.yh;
+      if (last)
+        pb.y = reinterpret_cast<float*>(obuf);
+      else
+        pb.yh = reinterpret_cast<uint16_t*>(obuf);
+      LAUNCH(nm("bbh_conva_bf16", "S", s), st, gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
+      LAUNCH(nm("bbh_convb_bf16", "S", s), st,
+             gw::launch_conv_bf16(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
     } else {
-      HIPCHK(gw::launch_conv_fp32(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
-      HIPCHK(gw::launch_conv_fp32(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
+      pa.x = reinterpret_cast<const float*>(cur);
+      pa.y = reinterpret_cast<float*>(hbuf);
+      pb.x = pa.y;
+      pb.xs = reinterpret_cast<const float*>(cur);
+      pb.y = reinterpret_cast<float*>(obuf);
+      LAUNCH(nm("bbh_conva_fp32", "S", s), st, gw::launch_conv_fp32(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
+      LAUNCH(nm("bbh_convb_fp32", "S", s), st,
+             gw::launch_conv_fp32(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
     }
-    in = pb.y;
+    cur = obuf;
     L = Lo;
   }
-  HIPCHK(gw::launch_gap_linear(in, P + m->head_w, P + m->head_b, logits, n, m->c_last, L, st));
+  in = reinterpret_cast<const float*>(cur);
+  LAUNCH("gap_linear", st, gw::launch_gap_linear(in, P + m->head_w, P + m->head_b, logits, n, m->c_last, L, st));
   return GW_OK;
 }

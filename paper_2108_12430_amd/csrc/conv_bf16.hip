@@ -1,14 +1,361 @@
-// BF16 MFMA implicit-GEMM convolutions (not yet built: every shape reports
-// unsupported and the ABI returns GW_EUNSUPPORTED for GW_BF16).
+// BF16 implicit-GEMM 1-D convolutions on the gfx950 matrix cores.
+//
+// GEMM view of one layer and one window:  Y[o][c] = sum_kappa A[o][kappa] B[kappa][c]
+//   o      output channel (M, tiles of 16)
+//   c      output column: the output time t for a strided conv, or the input
+//          position m for a stride-2 transposed conv (polyphase: column m
+//          produces outputs 2m and 2m+1 from two weight sets ("phases"), so the
+//          zeros a transposed conv would insert are never multiplied)
+//   kappa  = tap * CIP + input channel (K, channel-minor; CIP = C_in rounded up
+//          to a multiple of 8 so one lane's 8 consecutive K entries are one
+//          tap and 8 consecutive channels)
+// A (weights) is pre-packed in the exact per-lane fragment order of
+// v_mfma_f32_16x16x32_bf16 (16 bytes per lane per fragment).  B is read from
+// an LDS tile that holds the block's input window transposed to
+// [time][channel], so each lane's B fragment is one aligned 16-byte LDS read.
+// Accumulation is FP32; the epilogue (folded normalisation + tanh, ReLU,
+// residual shortcut, causal slice + subtraction) is FP32; intermediate
+// activations are stored as BF16 (round to nearest even).
+//
+// Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l = 0..63):
+//   A[row = l % 16][k = 8 (l / 16) + e],  B[k = 8 (l / 16) + e][col = l % 16],
+//   D[row = 4 (l / 16) + r][col = l % 16],  e = 0..7, r = 0..3.
 #include "internal.h"
 
 namespace gw {
 
-bool conv_bf16_supported(int, int, int, int, bool) { return false; }
-size_t conv_bf16_packed_elems(int, int, int, bool) { return 0; }
-hipError_t launch_pack_bf16(const float*, uint16_t*, int, int, int, bool, hipStream_t) {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+enum InFmt { IN_F32 = 0, IN_BF16 = 1, IN_RING = 2 };
+
+// Geometry of the polyphase/strided column view of a layer (host + device).
+struct Geo {
+  int nph;    // phases (1 for conv, stride for transposed)
+  int kt;     // taps per phase
+  int sc;     // input step per column (stride for conv, 1 for transposed)
+  int padc;   // input position of tile row 0 is sc*col0 - padc
+  int ncol;   // output columns
+};
+
+__host__ __device__ inline Geo make_geo(bool tr, int k, int s, int p, int Lout) {
+  Geo g;
+  if (!tr) {
+    g.nph = 1;
+    g.kt = k;
+    g.sc = s;
+    g.padc = p;
+    g.ncol = Lout;
+  } else {
+    // output u = s*m + r uses input m + d with tap j = r + p - s*d, 0 <= j < k
+    int dmin = 1 << 30, dmax = -(1 << 30);
+    for (int r = 0; r < s; ++r)
+      for (int j = 0; j < k; ++j)
+        if ((r + p - j) % s == 0) {
+          const int d = (r + p - j) / s;
+          dmin = d < dmin ? d : dmin;
+          dmax = d > dmax ? d : dmax;
+        }
+    g.nph = s;
+    g.kt = dmax - dmin + 1;
+    g.sc = 1;
+    g.padc = -dmin;
+    g.ncol = (Lout + s - 1) / s;
+  }
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing: fragment (ph, mt, ks), lane l, element e holds
+// W_ph[o = 16 mt + l%16][kappa = 32 ks + 8 (l/16) + e], zero outside.
+// ---------------------------------------------------------------------------
+static inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
+
+__global__ void pack_bf16_kernel(const float* w, uint16_t* out, int Ci, int Co, int k, int s, int p,
+                                 bool tr, int nph, int kt, int padc, int MT, int KS, int CIP,
+                                 int total) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int e = idx & 7;
+  const int l = (idx >> 3) & 63;
+  int f = idx >> 9;
+  const int ks = f % KS;
+  f /= KS;
+  const int mt = f % MT;
+  const int ph = f / MT;
+  const int o = 16 * mt + (l & 15);
+  const int kappa = 32 * ks + 8 * (l >> 4) + e;
+  const int jj = kappa / CIP, i = kappa % CIP;
+  float v = 0.0f;
+  if (o < Co && i < Ci && jj < kt) {
+    if (!tr) {
+      v = w[((int64_t)o * Ci + i) * k + jj];
+    } else {
+      const int d = jj - padc;
+      const int j = ph + p - s * d;
+      if (j >= 0 && j < k) v = w[((int64_t)i * Co + o) * k + j];
+    }
+  }
+  out[idx] = bf16_rne(v);
+}
+
+static void frag_dims(int Ci, int Co, int k, int s, int p, bool tr, int* MT, int* KS, int* CIP,
+                      Geo* g) {
+  *g = make_geo(tr, k, s, p, 1 << 20);
+  *CIP = cip_of(Ci);
+  *MT = (Co + 15) / 16;
+  *KS = (g->kt * *CIP + 31) / 32;
+}
+
+size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool tr) {
+  // stride/pad of the supported layers: conv k7 s{1,2} p3, transposed k7 s2 p3
+  int MT, KS, CIP;
+  Geo g;
+  frag_dims(Ci, Co, k, tr ? 2 : 1, 3, tr, &MT, &KS, &CIP, &g);
+  return (size_t)g.nph * MT * KS * 512;
+}
+
+hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool tr,
+                            hipStream_t st) {
+  const int s = tr ? 2 : 1, p = 3;
+  int MT, KS, CIP;
+  Geo g;
+  frag_dims(Ci, Co, k, s, p, tr, &MT, &KS, &CIP, &g);
+  const int total = g.nph * MT * KS * 512;
+  hipLaunchKernelGGL(pack_bf16_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, Ci, Co, k, s,
+                     p, tr, g.nph, g.kt, g.padc, MT, KS, CIP, total);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The convolution kernel.  Block = 4 waves; the block owns TN = 64*NTW
+// consecutive columns of one window and all output channels.
+// ---------------------------------------------------------------------------
+template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32>
+__global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
+  constexpr int TN = 64 * NTW;
+  constexpr int ROWS = SC * (TN - 1) + KT;
+  constexpr int RS = CIP + 8;  // LDS row stride in bf16 (16-byte multiple, skews banks)
+  constexpr int KS = (KT * CIP + 31) / 32;
+  __shared__ __attribute__((aligned(16))) uint16_t tile[(ROWS + 1) * RS];
+
+  const int b = blockIdx.y;
+  const int col0 = blockIdx.x * TN;
+  const int q0 = SC * col0 - padc;  // input position of tile row 0
+  const int tid = threadIdx.x;
+
+  // ---- stage the input window [ROWS][CIP] (time-major) in LDS as bf16
+  {
+    const Item* it = (IN == IN_RING) ? &p.items[b] : nullptr;
+    const int Ci = p.Ci, Lin = p.Lin;
+    for (int e = tid; e < ROWS * CIP; e += 256) {
+      const int i = e / ROWS, r = e - i * ROWS;
+      const int q = q0 + r;
+      uint16_t v = 0;
+      if (i < Ci && q >= 0 && q < Lin) {
+        if (IN == IN_F32) {
+          v = bf16_rne(p.x[((int64_t)b * Ci + i) * Lin + q]);
+        } else if (IN == IN_BF16) {
+          v = p.xh[((int64_t)b * Ci + i) * Lin + q];
+        } else {
+          int ph = it->head + q;
+          if (ph >= Lin) ph -= Lin;
+          v = reinterpret_cast<const uint16_t*>(p.arena)[it->shadow + (int64_t)i * Lin + ph];
+        }
+      }
+      tile[r * RS + i] = v;
+    }
+    for (int e = tid; e < RS; e += 256) tile[ROWS * RS + e] = 0;  // zero row for padded K
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lc = lane & 15, lg = lane >> 4;
+  const uint4* wp = reinterpret_cast<const uint4*>(p.wpk);
+
+  f32x4 acc[NTW][NPH][MT];
+#pragma unroll
+  for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+    for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kappa = 32 * ks + 8 * lg;
+    const int jj = kappa / CIP, i0 = kappa - jj * CIP;
+    uint4 af[NPH][MT];
+#pragma unroll
+    for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[ph][mt] = wp[((ph * MT + mt) * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) {
+      const int c = (wave * NTW + nt) * 16 + lc;
+      const int row = (jj < KT) ? SC * c + jj : ROWS;
+      const uint4 bv = *reinterpret_cast<const uint4*>(&tile[row * RS + i0]);
+      const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+      for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
+    }
+  }
+
+  // ---- epilogue
+#pragma unroll
+  for (int nt = 0; nt < NTW; ++nt) {
+    const int col = col0 + (wave * NTW + nt) * 16 + lc;
+    if (col >= ncol) continue;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * mt + 4 * lg + r;
+        if (o >= p.Co) continue;
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph) {
+          const int u = NPH * col + ph;  // output position
+          if (u >= p.Lout) continue;
+          const float a = acc[nt][ph][mt][r];
+          float v;
+          if (EPI == EPI_AFFINE || EPI == EPI_OUT) {
+            v = fmaf(a, p.scale[o], p.shift[o]);
+          } else if (EPI == EPI_AFFINE_TANH) {
+            v = tanhf(fmaf(a, p.scale[o], p.shift[o]));
+          } else if (EPI == EPI_RELU) {
+            v = fmaxf(a + p.bias[o], 0.0f);
+          } else if (EPI == EPI_BIAS) {
+            v = p.bias ? a + p.bias[o] : a;
+          } else {  // EPI_RESID_RELU: 1x1 stride-2 projection of the stage input, FP32
+            float sc = 0.0f;
+            for (int i = 0; i < p.Cs; ++i) {
+              const int64_t xi = ((int64_t)b * p.Cs + i) * p.Ls + 2 * u;
+              const float xv = XS_F32 ? bf16_to_f(bf16_rne(p.xs[xi])) : bf16_to_f(p.xsh[xi]);
+              sc = fmaf(p.ws[o * p.Cs + i], xv, sc);
+            }
+            v = fmaxf((a + p.bias[o]) + (sc + p.bs[o]), 0.0f);
+          }
+          if (EPI == EPI_OUT) {
+            const int W = p.Lout;
+            if (p.noise) p.noise[(int64_t)b * W + u] = v;
+            if (p.clean) {
+              const Item& it = p.items[b];
+              const int t0 = W - it.s;
+              if (u >= t0) {
+                const int64_t idx = it.out + (u - t0);
+                p.clean[idx] = p.strain[idx] - v;
+              }
+            }
+          } else if (OUT_F32) {
+            p.y[((int64_t)b * p.Co + o) * p.Lout + u] = v;
+          } else {
+            p.yh[((int64_t)b * p.Co + o) * p.Lout + u] = bf16_rne(v);
+          }
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over the instantiated shapes.
+// ---------------------------------------------------------------------------
+struct Key {
+  int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32;
+};
+
+template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32>
+static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
+  constexpr int NTW = (NPH * MT <= 4) ? 4 : 2;
+  constexpr int TN = 64 * NTW;
+  dim3 grid((g.ncol + TN - 1) / TN, p.n);
+  hipLaunchKernelGGL((conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32>), grid, dim3(256), 0, st,
+                     p, g.padc, g.ncol);
+  return hipGetLastError();
+}
+
+// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32) of every compiled variant.
+#define GW_BF16_VARIANTS(X)                                              \
+  /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */ \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false)              \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false)             \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false)               \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false)              \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)              \
+  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)             \
+  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)             \
+  /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */           \
+  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
+  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
+  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
+  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)              \
+  /* output conv k7 s1 with causal slice + subtraction */               \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false)                       \
+  /* BBHnet-shaped stages */                                            \
+  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false)                      \
+  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true)               \
+  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false)                    \
+  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false)              \
+  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false)                    \
+  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false)
+
+static bool find_variant(const Key& k) {
+#define GW_MATCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF)                                          \
+  if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
+      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF)                               \
+    return true;
+  GW_BF16_VARIANTS(GW_MATCH)
+#undef GW_MATCH
+  return false;
+}
+
+bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
+  // shape-level check: some variant exists for these channels and geometry
+  if (k != 7) return false;
+  if (tr && stride != 2) return false;
+  const Geo g = make_geo(tr, k, stride, 3, 1 << 20);
+  const int cip = cip_of(Ci), mt = (Co + 15) / 16;
+#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF) \
+  if (cip == CIP && mt == MT && g.nph == NPH && g.kt == KT && g.sc == SC) return true;
+  GW_BF16_VARIANTS(GW_SHAPE)
+#undef GW_SHAPE
+  return false;
+}
+
+// The ABI passes: input format through p.x (fp32), p.xh (bf16) or ring
+// (src == SRC_RING); output fp32 when p.y is set and p.yh is not.
+hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream_t st) {
+  if (p.k != 7 || p.pad != 3) return hipErrorNotSupported;
+  const Geo g = make_geo(tr, p.k, p.stride, p.pad, p.Lout);
+  Key k;
+  k.cip = cip_of(p.Ci);
+  k.mt = (p.Co + 15) / 16;
+  k.nph = g.nph;
+  k.kt = g.kt;
+  k.sc = g.sc;
+  k.epi = epi;
+  k.in = src == SRC_RING ? IN_RING : (p.xh ? IN_BF16 : IN_F32);
+  k.out_f32 = (epi == EPI_OUT || p.yh == nullptr) ? 1 : 0;
+  if (epi == EPI_OUT) k.out_f32 = 1;
+  k.xs_f32 = (epi == EPI_RESID_RELU && p.xsh == nullptr) ? 1 : 0;
+#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF)                                         \
+  if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
+      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF)                               \
+    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF>(p, g, st);
+  GW_BF16_VARIANTS(GW_LAUNCH)
+#undef GW_LAUNCH
+  (void)find_variant;
   return hipErrorNotSupported;
 }
-hipError_t launch_conv_bf16(const ConvP&, bool, int, int, hipStream_t) { return hipErrorNotSupported; }
 
 }  // namespace gw

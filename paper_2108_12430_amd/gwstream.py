@@ -29,6 +29,7 @@ EXPORTS = [
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_n_params",
     "deepclean_workspace", "deepclean_forward", "deepclean_backward_scratch", "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "bbhnet_workspace", "bbhnet_forward",
+    "gw_profile_begin", "gw_profile_end",
 ]
 
 
@@ -74,6 +75,8 @@ def lib():
             "gw_bandpass_mse": ([i32, i32, f32, f32, f32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
             "bbhnet_workspace": ([vp, i32, i32, i32, P(sz)], C.c_int),
             "bbhnet_forward": ([vp, vp, vp, vp, i32, i32, vp, i32, vp, sz, vp], C.c_int),
+            "gw_profile_begin": ([], C.c_int),
+            "gw_profile_end": ([C.c_char_p, sz], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -345,3 +348,19 @@ def bandpass_mse(strain, noise, fs=4096.0, f_lo=55.0, f_hi=65.0, want_grad=True,
     check(lib().gw_bandpass_mse(n, W, fs, f_lo, f_hi, _ptr(_f32(strain, "strain")), _ptr(_f32(noise, "noise")),
                                 _ptr(loss), _ptr(dn), _ptr(ws), ws.numel(), _stream(stream)))
     return loss, dn
+
+
+def profile_begin():
+    """Start recording per-launch HIP-event timings inside the library."""
+    check(lib().gw_profile_begin())
+
+
+def profile_end():
+    """Stop recording; returns {launch name: (count, total_ms)}."""
+    buf = C.create_string_buffer(1 << 16)
+    check(lib().gw_profile_end(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -68,3 +68,23 @@ def test_bbhnet_from_pool_bitwise(bb):
     got_d = m.forward(x=torch.from_numpy(dense).to(DEV)).cpu().numpy()
     assert np.array_equal(got, got_d)
     assert rel(got, ref.bbhnet_forward(params, dense)) <= 1e-5
+
+
+@pytest.mark.parametrize("B", [64, 256, 1024])
+def test_bbhnet_bf16(bb, B):
+    """BF16 MFMA convolutions with FP32 accumulation, epilogue and logits."""
+    m, params = bb
+    x, _ = synth.bbh_windows(3 + B, B)
+    got = m.forward(x=torch.from_numpy(x).to(DEV), precision=gs.BF16).cpu().numpy()
+    idx = np.sort(np.random.default_rng(B + 1).choice(B, size=min(B, 64), replace=False))
+    exp = ref.bbhnet_forward(params, x[idx])
+    assert rel(got[idx], exp) <= 2e-2
+
+
+def test_bbhnet_bf16_batch_independent(bb):
+    m, _ = bb
+    x, _ = synth.bbh_windows(77, 40)
+    xt = torch.from_numpy(x).to(DEV)
+    full = m.forward(x=xt, precision=gs.BF16)
+    part = m.forward(x=xt[7:19].contiguous(), precision=gs.BF16)
+    assert torch.equal(full[7:19], part)

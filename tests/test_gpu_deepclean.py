@@ -85,9 +85,9 @@ def test_batch_independence_bitwise(dc):
 
 def test_invalid_calls(dc):
     m, _, _ = dc
-    x = torch.zeros((1, 21, 4000), device=DEV)   # 4000 is not a multiple of 16
+    x = torch.zeros((1, 21, 4008), device=DEV)   # 4008 is not a multiple of 16
     with pytest.raises(gs.GwError) as e:
-        m.forward(x=x, noise=torch.empty((1, 4000), device=DEV), ws=torch.empty(1 << 20, dtype=torch.uint8,
+        m.forward(x=x, noise=torch.empty((1, 4008), device=DEV), ws=torch.empty(1 << 20, dtype=torch.uint8,
                                                                                    device=DEV))
     assert e.value.code == gs.GW_EINVAL
     x = torch.zeros((1, 21, 4096), device=DEV)
@@ -157,7 +157,7 @@ def test_snapshot_batched_many_streams():
 def test_pool_admission_and_errors():
     C_, W = 21, 4096
     per = 21 * 4096 * 6
-    pool = gs.Pool(2 * per + (1 << 20), max_slots=8, max_items=8)
+    pool = gs.Pool(2 * per + (1 << 16), max_slots=8, max_items=8)
     a = pool.open(C_, W)
     b = pool.open(C_, W)
     assert pool.try_open(C_, W) is None                      # arena full -> GW_ENOMEM
@@ -245,3 +245,43 @@ def test_clean_output_mixed_strides(dc):
         _, ec = ref.causal_clean(exp_noise[i:i + 1], strain[None, o:o + s])
         assert rel(got[o:o + s], ec[0]) <= FP32_TOL
         o += s
+
+
+# --------------------------------------------------------------------------- BF16 MFMA path
+BF16_TOL = 2e-2
+
+
+@pytest.mark.parametrize("n,W", [(1, 4096), (3, 4096), (2, 32768), (2, 16 * 67)])
+def test_forward_bf16(dc, n, W):
+    """BF16 operands, FP32 accumulation and epilogue, BF16 activations."""
+    m, params, layers = dc
+    w, _ = synth.witness_stream(70 + n, n * W)
+    x = np.ascontiguousarray(w.reshape(21, n, W).transpose(1, 0, 2))
+    got = run_dense(m, x, gs.BF16)
+    exp = ref.deepclean_forward(params, x, layers)
+    assert rel(got, exp) <= BF16_TOL
+
+
+def test_streaming_bf16_bitwise(dc):
+    """BF16 path: windows read from the rings' BF16 shadow give bitwise the
+    same output as the dense offline forward of the same window."""
+    m, params, layers = dc
+    W, s, N = 32768, 256, 300
+    wit, strain = synth.witness_stream(12, N * s)
+    wit_t = torch.from_numpy(wit).to(DEV)
+    pool = gs.Pool(64 << 20, max_slots=2, max_items=2)
+    slot = pool.open(21, W)
+    ws = torch.empty(m.workspace_bytes(1, W, gs.BF16), dtype=torch.uint8, device=DEV)
+    noise_all = torch.empty((N, W), dtype=torch.float32, device=DEV)
+    for u in range(N):
+        pool.update([slot], [s], wit_t[:, u * s:(u + 1) * s].contiguous().reshape(-1), [0])
+        m.forward(pool=pool, slots=[slot], W=W, noise=noise_all[u], precision=gs.BF16, ws=ws)
+    zp = torch.cat([torch.zeros((21, W), device=DEV), wit_t], dim=1)
+    off = torch.empty((50, W), dtype=torch.float32, device=DEV)
+    for u0 in range(0, N, 50):
+        xs = torch.stack([zp[:, (u + 1) * s:(u + 1) * s + W] for u in range(u0, u0 + 50)]).contiguous()
+        m.forward(x=xs, noise=off, precision=gs.BF16)
+        assert torch.equal(off, noise_all[u0:u0 + 50]), f"updates {u0}..{u0 + 49}"
+    check = [0, 127, 128, N - 1]
+    xs = np.stack([ref.snapshot_after(wit, (u + 1) * s, W) for u in check])
+    assert rel(noise_all[check].cpu().numpy(), ref.deepclean_forward(params, xs, layers)) <= BF16_TOL
