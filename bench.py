@@ -137,6 +137,95 @@ def cpu_baseline(dc_s, bb_s, budget_s=12.0):
                       f"full-window recompute per request), {dt:.1f} s"}
 
 
+def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
+    """Serving loop (continuous batching, host requests staged through pinned
+    memory, so PCIe-inclusive) on the same 256-stream mix: a closed-loop run
+    and open-loop Poisson arrivals at the given aggregate update rates."""
+    import torch
+
+    from paper_2108_12430_amd.serve import HipExecutor, Server
+    from paper_2108_12430_amd import synth
+
+    rng = np.random.default_rng(6)
+    src = synth.gaussian(8, (DC_C, 1 << 18))
+    src_s = synth.gaussian(9, (1 << 18,))
+    specs = [("dc", DC_C, DC_W, int(s)) for s in dc_s] + [("bbh", BB_C, BB_W, int(s)) for s in bb_s]
+    ring = lambda c, w: ((c * w * 4 + 255) // 256 + (c * w * 2 + 255) // 256) * 256
+    arena = N_DC * ring(DC_C, DC_W) + N_BB * ring(BB_C, BB_W) + (64 << 20)
+    out = {}
+
+    def sample(i, k):
+        model, C, W, s = specs[i]
+        o = (i * 7919 + k * s) % ((1 << 18) - 1024)
+        return src[:C, o:o + s], (src_s[o:o + s] if model == "dc" else None)
+
+    def run(arrivals, closed):
+        ex = HipExecutor({"dc": dc, "bbh": bb}, arena_bytes=arena, max_slots=len(specs),
+                         max_items=len(specs), precision=prec)
+        srv = Server(ex, max_inflight=4)
+        sids = [srv.open_stream(m, C, W) for (m, C, W, s) in specs]
+        # warm-up: one request per stream
+        for i, sid in enumerate(sids):
+            x, st = sample(i, 0)
+            srv.submit(sid, x, st)
+        srv.drain()
+        srv.completed.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nsamp = 0
+        if closed:
+            k = 1
+            while time.perf_counter() - t0 < seconds:
+                for i, sid in enumerate(sids):
+                    x, st = sample(i, k)
+                    srv.submit(sid, x, st)
+                    nsamp += specs[i][3]
+                srv.step()
+                k += 1
+            srv.drain()
+        else:
+            idx = 0
+            cnt = [1] * len(specs)
+            while idx < len(arrivals) or srv.pending() or srv.inflight:
+                now = time.perf_counter() - t0
+                while idx < len(arrivals) and arrivals[idx][0] <= now:
+                    ta, i = arrivals[idx]
+                    x, st = sample(i, cnt[i])
+                    cnt[i] += 1
+                    srv.submit(sids[i], x, st, t_arrival=t0 + ta)
+                    nsamp += specs[i][3]
+                    idx += 1
+                if srv.pending():
+                    srv.step()
+                else:
+                    srv.poll()
+        dt = time.perf_counter() - t0
+        st_ = srv.latency_stats()
+        st_["samples_per_s"] = nsamp / dt
+        st_["steps"] = srv.steps
+        return st_
+
+    out["closed_loop"] = run(None, True)
+    log_fn(f"bench: serving closed loop {out['closed_loop']}")
+    strides = np.array([s for *_, s in specs], np.float64)
+    w = 1.0 / strides
+    out["open_loop"] = []
+    for lam in rates:
+        per = lam * w / w.sum()   # per-stream Poisson rates proportional to 1/stride
+        arr = []
+        for i, r in enumerate(per):
+            t = rng.exponential(1.0 / r)
+            while t < seconds:
+                arr.append((t, i))
+                t += rng.exponential(1.0 / r)
+        arr.sort()
+        res = run(arr, False)
+        res["rate"] = lam
+        out["open_loop"].append(res)
+        log_fn(f"bench: serving open loop {lam}/s: {res}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +237,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="1000,5000,20000")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -256,8 +350,20 @@ def main():
         torch.cuda.synchronize()
         lat.append(1e3 * (time.perf_counter() - t1))
         k += 1
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.zeros(1)
     log(f"bench: latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    if args.copy_calibration:
+        # a plain copy of known size, so hardware byte counters can be scaled
+        nb = args.copy_calibration << 20
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration {args.copy_calibration} MiB x 3")
+        del a, c
 
     roof = None
     if not args.no_roofline:
@@ -323,6 +429,11 @@ def main():
                  "dtype": "f32", "batching": "one stream per launch"}
         log(f"bench: fp32 plain {plain['value']:.4g} samples/s, p99 {plain['p99_ms']:.3f} ms")
 
+    serving = None
+    if not args.no_serve:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        serving = serve_bench(dc, bb, prec, dc_s, bb_s, rates, args.serve_seconds, log)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(dc_s, bb_s)
@@ -339,7 +450,7 @@ def main():
                    "channel_samples_per_step": int(DC_C * dc_s.sum() + BB_C * bb_s.sum())},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
-        "fp32_plain": plain, "roofline": roof, "cpu_baseline": cpu,
+        "fp32_plain": plain, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -387,7 +387,7 @@ struct LayerD {
 struct StageD {
   int ci, co;
   int64_t wa, ba, wb, bb, ws, bs;
-  size_t wa_bf, wb_bf;
+  size_t wa_bf, wb_bf, ws_bf;
   bool bf16;
 };
 
@@ -500,6 +500,8 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
         pk += r256(2 * gw::conv_bf16_packed_elems(sd.ci, sd.co, 7, false));
         sd.wb_bf = pk;
         pk += r256(2 * gw::conv_bf16_packed_elems(sd.co, sd.co, 7, false));
+        sd.ws_bf = pk;
+        pk += r256(2 * gw::conv_bf16_packed_elems(sd.ci, sd.co, 1, false));
       }
       m.bf16_all = m.bf16_all && sd.bf16;
       m.stages.push_back(sd);
@@ -539,6 +541,8 @@ int pack_model(gw_model* m, hipStream_t st) {
                                   sd.co, 7, false, st));
       HIPCHK(gw::launch_pack_bf16(P + sd.wb, reinterpret_cast<uint16_t*>(m->packed + sd.wb_bf), sd.co,
                                   sd.co, 7, false, st));
+      HIPCHK(gw::launch_pack_bf16(P + sd.ws, reinterpret_cast<uint16_t*>(m->packed + sd.ws_bf), sd.ci,
+                                  sd.co, 1, false, st));
     }
   }
   return GW_OK;
@@ -1125,7 +1129,7 @@ extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float
 // ===========================================================================
 namespace {
 struct BbWs {
-  size_t gath = NONE, h = 0, o[2] = {0, 0}, total = 0;
+  size_t gath = NONE, h = 0, o[2] = {0, 0}, gap = 0, total = 0;
 };
 int bb_layout(const gw_model* m, int n, int W, bool pool, int precision, BbWs& b) {
   const int Sn = (int)m->stages.size();
@@ -1147,6 +1151,7 @@ int bb_layout(const gw_model* m, int n, int W, bool pool, int precision, BbWs& b
   b.h = take(mh);
   b.o[0] = take(mh);
   b.o[1] = take(mh);
+  b.gap = take((size_t)n * 64 * sizeof(float));
   b.total = off;
   return GW_OK;
 }
@@ -1248,6 +1253,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     if (bf) {
       pa.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wa_bf);
       pb.wpk = reinterpret_cast<const uint16_t*>(m->packed + sd.wb_bf);
+      pb.wspk = reinterpret_cast<const uint16_t*>(m->packed + sd.ws_bf);
       if (s == 0) {
         pa.x = reinterpret_cast<const float*>(cur);
         pb.xs = reinterpret_cast<const float*>(cur);
@@ -1257,13 +1263,24 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       }
       pa.yh = reinterpret_cast<uint16_t*>(hbuf);
       pb.xh = pa.yh;
-      if (last)
-        pb.y = reinterpret_cast<float*>(obuf);
-      else
+      int epi_b = gw::EPI_RESID_RELU;
+      if (last) {
+        // last stage: the pooling head is fused into the epilogue
+        const int nblk = (Lo + gw::conv_bf16_col_tile(sd.co, false) - 1) / gw::conv_bf16_col_tile(sd.co, false);
+        if (nblk > 64) return fail(GW_EUNSUPPORTED, "window too long for the fused pooling head");
+        pb.hw = P + m->head_w;
+        pb.gap_part = reinterpret_cast<float*>(wsb + b.gap);
+        epi_b = gw::EPI_RESID_GAP;
+      } else {
         pb.yh = reinterpret_cast<uint16_t*>(obuf);
+      }
       LAUNCH(nm("bbh_conva_bf16", "S", s), st, gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
-      LAUNCH(nm("bbh_convb_bf16", "S", s), st,
-             gw::launch_conv_bf16(pb, false, gw::EPI_RESID_RELU, gw::SRC_DENSE, st));
+      LAUNCH(nm("bbh_convb_bf16", "S", s), st, gw::launch_conv_bf16(pb, false, epi_b, gw::SRC_DENSE, st));
+      if (last) {
+        const int nblk = (Lo + gw::conv_bf16_col_tile(sd.co, false) - 1) / gw::conv_bf16_col_tile(sd.co, false);
+        LAUNCH("gap_finalize", st,
+               gw::launch_gap_finalize(pb.gap_part, nblk, P + m->head_b, logits, n, Lo, st));
+      }
     } else {
       pa.x = reinterpret_cast<const float*>(cur);
       pa.y = reinterpret_cast<float*>(hbuf);
@@ -1278,6 +1295,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     L = Lo;
   }
   in = reinterpret_cast<const float*>(cur);
+  if (bf) return GW_OK;  // BF16: the pooling head ran in the last stage's epilogue
   LAUNCH("gap_linear", st, gw::launch_gap_linear(in, P + m->head_w, P + m->head_b, logits, n, m->c_last, L, st));
   return GW_OK;
 }

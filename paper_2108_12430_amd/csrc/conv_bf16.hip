@@ -136,48 +136,166 @@ hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k
 }
 
 // ---------------------------------------------------------------------------
-// The convolution kernel.  Block = 4 waves; the block owns TN = 64*NTW
-// consecutive columns of one window and all output channels.
+// LDS staging.  Tile row r holds input position q0 + r for every channel
+// (time-major, channel-minor, row stride RS).  Work items are (channel,
+// 8-position chunk) with the channel varying fastest across lanes, so the
+// 2-byte LDS stores of one instruction hit consecutive banks; each item reads
+// its 8 positions with one 16-byte load (32 bytes for FP32 input) when the
+// chunk is aligned and inside the signal, element by element otherwise.
 // ---------------------------------------------------------------------------
-template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32>
+template <int CIP, int ROWS, int RS, int IN>
+__device__ __forceinline__ void stage_input(uint16_t* tile, const ConvP& p, int b, int q0) {
+  // upper bound of (channel, chunk) items per thread; all of a thread's
+  // global loads are issued before any LDS store so they are in flight together
+  constexpr int NCHMAX = (ROWS + 7 + 7) / 8;
+  constexpr int ITEMS = (NCHMAX * CIP + 255) / 256;
+  const int Ci = p.Ci, Lin = p.Lin;
+  const int qa = q0 - (((q0 % 8) + 8) % 8);  // floor to a multiple of 8
+  const int nch = (q0 + ROWS - qa + 7) / 8;
+  int head = 0;
+  const uint16_t* hbase = nullptr;
+  const float* fbase = nullptr;
+  bool vec = (Lin & 7) == 0;
+  if (IN == IN_RING) {
+    const Item& it = p.items[b];
+    head = it.head;
+    hbase = reinterpret_cast<const uint16_t*>(p.arena) + it.shadow;
+    vec = vec && (head & 7) == 0 && (it.shadow & 7) == 0;
+  } else if (IN == IN_BF16) {
+    hbase = p.xh + (int64_t)b * Ci * Lin;
+    vec = vec && (reinterpret_cast<uintptr_t>(p.xh) & 15) == 0;
+  } else {
+    fbase = p.x + (int64_t)b * Ci * Lin;
+    vec = vec && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
+  }
+  uint4 raw[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    const int i = e % CIP, ch = e / CIP;
+    const int qc = qa + 8 * ch;
+    uint16_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = 0;
+    if (ch < nch && i < Ci) {
+      if (vec && qc >= 0 && qc + 8 <= Lin) {
+        if (IN == IN_F32) {
+          const float4* src = reinterpret_cast<const float4*>(fbase + (int64_t)i * Lin + qc);
+          const float4 a = src[0], c = src[1];
+          v[0] = bf16_rne(a.x); v[1] = bf16_rne(a.y); v[2] = bf16_rne(a.z); v[3] = bf16_rne(a.w);
+          v[4] = bf16_rne(c.x); v[5] = bf16_rne(c.y); v[6] = bf16_rne(c.z); v[7] = bf16_rne(c.w);
+        } else {
+          int ph = qc;
+          if (IN == IN_RING) {
+            ph = head + qc;
+            if (ph >= Lin) ph -= Lin;
+          }
+          const uint4 u = *reinterpret_cast<const uint4*>(hbase + (int64_t)i * Lin + ph);
+          raw[it] = u;
+          continue;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = qc + k;
+          if (q >= 0 && q < Lin) {
+            if (IN == IN_F32) {
+              v[k] = bf16_rne(fbase[(int64_t)i * Lin + q]);
+            } else {
+              int ph = q;
+              if (IN == IN_RING) {
+                ph = head + q;
+                if (ph >= Lin) ph -= Lin;
+              }
+              v[k] = hbase[(int64_t)i * Lin + ph];
+            }
+          }
+        }
+      }
+    }
+    raw[it].x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    raw[it].y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    raw[it].z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+    raw[it].w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    const int i = e % CIP, ch = e / CIP;
+    if (ch >= nch) continue;
+    const int r0 = qa + 8 * ch - q0;
+    const uint32_t w[4] = {raw[it].x, raw[it].y, raw[it].z, raw[it].w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + k;
+      if (r >= 0 && r < ROWS) tile[r * RS + i] = (uint16_t)(w[k >> 1] >> (16 * (k & 1)));
+    }
+  }
+  for (int e = threadIdx.x; e < RS; e += 256) tile[ROWS * RS + e] = 0;  // zero row for padded K
+}
+
+// Shortcut tile for the residual stage: row c holds the stage input at
+// position 2 (col0 + c) (1x1 kernel, stride 2), channel-minor.
+template <int CSP, int TN, int RSX, bool XS_F32>
+__device__ __forceinline__ void stage_shortcut(uint16_t* xt, const ConvP& p, int b, int col0) {
+  const int Cs = p.Cs, Ls = p.Ls;
+  const int p0 = 2 * col0;  // multiple of 8
+  const bool vec = (Ls & 7) == 0 &&
+                   ((XS_F32 ? reinterpret_cast<uintptr_t>(p.xs) : reinterpret_cast<uintptr_t>(p.xsh)) & 15) == 0;
+  for (int e = threadIdx.x; e < (TN / 4) * CSP; e += 256) {
+    const int i = e % CSP, ch = e / CSP;
+    const int pc = p0 + 8 * ch;  // positions pc .. pc+7 -> rows 4ch .. 4ch+3 (even positions)
+    uint16_t v[4] = {0, 0, 0, 0};
+    if (i < Cs) {
+      const int64_t base = ((int64_t)b * Cs + i) * Ls;
+      if (vec && pc + 8 <= Ls) {
+        if (XS_F32) {
+          const float4* src = reinterpret_cast<const float4*>(p.xs + base + pc);
+          const float4 a = src[0], c = src[1];
+          v[0] = bf16_rne(a.x); v[1] = bf16_rne(a.z); v[2] = bf16_rne(c.x); v[3] = bf16_rne(c.z);
+        } else {
+          const uint4 u = *reinterpret_cast<const uint4*>(p.xsh + base + pc);
+          v[0] = u.x & 0xffff; v[1] = u.y & 0xffff; v[2] = u.z & 0xffff; v[3] = u.w & 0xffff;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int q = pc + 2 * k;
+          if (q < Ls) v[k] = XS_F32 ? bf16_rne(p.xs[base + q]) : p.xsh[base + q];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xt[(4 * ch + k) * RSX + i] = v[k];
+  }
+  for (int e = threadIdx.x; e < RSX; e += 256) xt[TN * RSX + e] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// The convolution kernel.  Block = 4 waves; the block owns TN = 64*NTW
+// consecutive columns of one window and all output channels.  With CSP > 0
+// (residual stage) the 1x1 stride-2 shortcut of the stage input is added to
+// the same accumulators as extra K steps.
+// ---------------------------------------------------------------------------
+template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32,
+          int CSP>
 __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   constexpr int TN = 64 * NTW;
   constexpr int ROWS = SC * (TN - 1) + KT;
   constexpr int RS = CIP + 8;  // LDS row stride in bf16 (16-byte multiple, skews banks)
   constexpr int KS = (KT * CIP + 31) / 32;
+  constexpr int RSX = CSP + 8;
+  constexpr int KS2 = (CSP + 31) / 32;
   __shared__ __attribute__((aligned(16))) uint16_t tile[(ROWS + 1) * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t xt[CSP > 0 ? (TN + 1) * RSX : 8];
 
   const int b = blockIdx.y;
   const int col0 = blockIdx.x * TN;
-  const int q0 = SC * col0 - padc;  // input position of tile row 0
-  const int tid = threadIdx.x;
-
-  // ---- stage the input window [ROWS][CIP] (time-major) in LDS as bf16
-  {
-    const Item* it = (IN == IN_RING) ? &p.items[b] : nullptr;
-    const int Ci = p.Ci, Lin = p.Lin;
-    for (int e = tid; e < ROWS * CIP; e += 256) {
-      const int i = e / ROWS, r = e - i * ROWS;
-      const int q = q0 + r;
-      uint16_t v = 0;
-      if (i < Ci && q >= 0 && q < Lin) {
-        if (IN == IN_F32) {
-          v = bf16_rne(p.x[((int64_t)b * Ci + i) * Lin + q]);
-        } else if (IN == IN_BF16) {
-          v = p.xh[((int64_t)b * Ci + i) * Lin + q];
-        } else {
-          int ph = it->head + q;
-          if (ph >= Lin) ph -= Lin;
-          v = reinterpret_cast<const uint16_t*>(p.arena)[it->shadow + (int64_t)i * Lin + ph];
-        }
-      }
-      tile[r * RS + i] = v;
-    }
-    for (int e = tid; e < RS; e += 256) tile[ROWS * RS + e] = 0;  // zero row for padded K
-  }
+  stage_input<CIP, ROWS, RS, IN>(tile, p, b, SC * col0 - padc);
+  if (CSP > 0) stage_shortcut<CSP, TN, RSX, XS_F32>(xt, p, b, col0);
   __syncthreads();
 
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lg = lane >> 4;
   const uint4* wp = reinterpret_cast<const uint4*>(p.wpk);
 
@@ -211,8 +329,29 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
               __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
     }
   }
+  if (CSP > 0) {
+    const uint4* sp = reinterpret_cast<const uint4*>(p.wspk);
+    for (int ks = 0; ks < KS2; ++ks) {
+      const int kappa = 32 * ks + 8 * lg;
+      uint4 af[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[mt] = sp[(mt * KS2 + ks) * 64 + lane];
+#pragma unroll
+      for (int nt = 0; nt < NTW; ++nt) {
+        const int c = (wave * NTW + nt) * 16 + lc;
+        const int row = kappa < CSP ? c : TN;
+        const uint4 bv = *reinterpret_cast<const uint4*>(&xt[row * RSX + (kappa < CSP ? kappa : 0)]);
+        const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[nt][0][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[mt]), bb,
+                                                                   acc[nt][0][mt], 0, 0, 0);
+      }
+    }
+  }
 
   // ---- epilogue
+  float gsum = 0.0f;  // EPI_RESID_GAP: this lane's share of sum_o hw[o] y[o][t]
 #pragma unroll
   for (int nt = 0; nt < NTW; ++nt) {
     const int col = col0 + (wave * NTW + nt) * 16 + lc;
@@ -223,47 +362,69 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
       for (int r = 0; r < 4; ++r) {
         const int o = 16 * mt + 4 * lg + r;
         if (o >= p.Co) continue;
+        float v[NPH];
 #pragma unroll
         for (int ph = 0; ph < NPH; ++ph) {
-          const int u = NPH * col + ph;  // output position
-          if (u >= p.Lout) continue;
           const float a = acc[nt][ph][mt][r];
-          float v;
           if (EPI == EPI_AFFINE || EPI == EPI_OUT) {
-            v = fmaf(a, p.scale[o], p.shift[o]);
+            v[ph] = fmaf(a, p.scale[o], p.shift[o]);
           } else if (EPI == EPI_AFFINE_TANH) {
-            v = tanhf(fmaf(a, p.scale[o], p.shift[o]));
+            v[ph] = tanhf(fmaf(a, p.scale[o], p.shift[o]));
           } else if (EPI == EPI_RELU) {
-            v = fmaxf(a + p.bias[o], 0.0f);
+            v[ph] = fmaxf(a + p.bias[o], 0.0f);
           } else if (EPI == EPI_BIAS) {
-            v = p.bias ? a + p.bias[o] : a;
-          } else {  // EPI_RESID_RELU: 1x1 stride-2 projection of the stage input, FP32
-            float sc = 0.0f;
-            for (int i = 0; i < p.Cs; ++i) {
-              const int64_t xi = ((int64_t)b * p.Cs + i) * p.Ls + 2 * u;
-              const float xv = XS_F32 ? bf16_to_f(bf16_rne(p.xs[xi])) : bf16_to_f(p.xsh[xi]);
-              sc = fmaf(p.ws[o * p.Cs + i], xv, sc);
-            }
-            v = fmaxf((a + p.bias[o]) + (sc + p.bs[o]), 0.0f);
+            v[ph] = p.bias ? a + p.bias[o] : a;
+          } else {  // EPI_RESID_RELU / EPI_RESID_GAP: shortcut already accumulated
+            v[ph] = fmaxf(a + (p.bias[o] + p.bs[o]), 0.0f);
           }
-          if (EPI == EPI_OUT) {
+        }
+        if (EPI == EPI_RESID_GAP) {
+          gsum = fmaf(p.hw[o], v[0], gsum);
+          continue;
+        }
+        if (EPI == EPI_OUT) {
+#pragma unroll
+          for (int ph = 0; ph < NPH; ++ph) {
+            const int u = NPH * col + ph;
+            if (u >= p.Lout) continue;
             const int W = p.Lout;
-            if (p.noise) p.noise[(int64_t)b * W + u] = v;
+            if (p.noise) p.noise[(int64_t)b * W + u] = v[ph];
             if (p.clean) {
               const Item& it = p.items[b];
               const int t0 = W - it.s;
               if (u >= t0) {
                 const int64_t idx = it.out + (u - t0);
-                p.clean[idx] = p.strain[idx] - v;
+                p.clean[idx] = p.strain[idx] - v[ph];
               }
             }
-          } else if (OUT_F32) {
-            p.y[((int64_t)b * p.Co + o) * p.Lout + u] = v;
-          } else {
-            p.yh[((int64_t)b * p.Co + o) * p.Lout + u] = bf16_rne(v);
+          }
+        } else if (OUT_F32) {
+#pragma unroll
+          for (int ph = 0; ph < NPH; ++ph) {
+            const int u = NPH * col + ph;
+            if (u < p.Lout) p.y[((int64_t)b * p.Co + o) * p.Lout + u] = v[ph];
+          }
+        } else if (NPH == 2 && (p.Lout & 1) == 0) {
+          // both phases are adjacent outputs: one 4-byte store
+          const uint32_t w2 = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[NPH - 1]) << 16);
+          *reinterpret_cast<uint32_t*>(&p.yh[((int64_t)b * p.Co + o) * p.Lout + 2 * col]) = w2;
+        } else {
+#pragma unroll
+          for (int ph = 0; ph < NPH; ++ph) {
+            const int u = NPH * col + ph;
+            if (u < p.Lout) p.yh[((int64_t)b * p.Co + o) * p.Lout + u] = bf16_rne(v[ph]);
           }
         }
       }
+  }
+  if (EPI == EPI_RESID_GAP) {
+    // fixed-order reduction: lanes of a wave, then the four waves
+    for (int off = 32; off > 0; off >>= 1) gsum += __shfl_down(gsum, off, 64);
+    __shared__ float wsum[4];
+    if (lane == 0) wsum[wave] = gsum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      p.gap_part[(int64_t)b * gridDim.x + blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
   }
 }
 
@@ -271,52 +432,48 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
 // Dispatch over the instantiated shapes.
 // ---------------------------------------------------------------------------
 struct Key {
-  int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32;
+  int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32, csp;
 };
 
-template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32>
+template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32, int CSP>
 static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   constexpr int NTW = (NPH * MT <= 4) ? 4 : 2;
   constexpr int TN = 64 * NTW;
   dim3 grid((g.ncol + TN - 1) / TN, p.n);
-  hipLaunchKernelGGL((conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32>), grid, dim3(256), 0, st,
-                     p, g.padc, g.ncol);
+  hipLaunchKernelGGL((conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP>), grid, dim3(256), 0,
+                     st, p, g.padc, g.ncol);
   return hipGetLastError();
 }
 
-// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32) of every compiled variant.
-#define GW_BF16_VARIANTS(X)                                              \
-  /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */ \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false)              \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false)             \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false)               \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false)              \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)              \
-  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)             \
-  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false)             \
-  /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */           \
-  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
-  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
-  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)             \
-  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false)              \
-  /* output conv k7 s1 with causal slice + subtraction */               \
-  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false)                       \
-  /* BBHnet-shaped stages */                                            \
-  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false)                      \
-  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true)               \
-  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false)                    \
-  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false)              \
-  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false)                    \
-  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false)
+// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32, CSP) of every compiled variant.
+#define GW_BF16_VARIANTS(X)                                                  \
+  /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */     \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0)               \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0)              \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0)                \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0)               \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)               \
+  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
+  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
+  /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */               \
+  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
+  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
+  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
+  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)               \
+  /* output conv k7 s1 with causal slice + subtraction */                   \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false, 0)                        \
+  /* BBHnet-shaped stages: conv_a, then conv_b + 1x1 stride-2 shortcut */    \
+  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0)                       \
+  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8)                \
+  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0)                     \
+  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32)              \
+  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0)                     \
+  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64)             \
+  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64)
 
-static bool find_variant(const Key& k) {
-#define GW_MATCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF)                                          \
-  if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
-      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF)                               \
-    return true;
-  GW_BF16_VARIANTS(GW_MATCH)
-#undef GW_MATCH
-  return false;
+int conv_bf16_col_tile(int Co, bool tr) {
+  const int nph = tr ? 2 : 1, mt = (Co + 15) / 16;
+  return 64 * ((nph * mt <= 4) ? 4 : 2);
 }
 
 bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
@@ -325,7 +482,7 @@ bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
   if (tr && stride != 2) return false;
   const Geo g = make_geo(tr, k, stride, 3, 1 << 20);
   const int cip = cip_of(Ci), mt = (Co + 15) / 16;
-#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF) \
+#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS) \
   if (cip == CIP && mt == MT && g.nph == NPH && g.kt == KT && g.sc == SC) return true;
   GW_BF16_VARIANTS(GW_SHAPE)
 #undef GW_SHAPE
@@ -333,7 +490,8 @@ bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
 }
 
 // The ABI passes: input format through p.x (fp32), p.xh (bf16) or ring
-// (src == SRC_RING); output fp32 when p.y is set and p.yh is not.
+// (src == SRC_RING); output fp32 when p.y is set and p.yh is not; residual
+// shortcut input through p.xs (fp32) or p.xsh (bf16) with weights p.wspk.
 hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream_t st) {
   if (p.k != 7 || p.pad != 3) return hipErrorNotSupported;
   const Geo g = make_geo(tr, p.k, p.stride, p.pad, p.Lout);
@@ -346,15 +504,18 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
   k.epi = epi;
   k.in = src == SRC_RING ? IN_RING : (p.xh ? IN_BF16 : IN_F32);
   k.out_f32 = (epi == EPI_OUT || p.yh == nullptr) ? 1 : 0;
-  if (epi == EPI_OUT) k.out_f32 = 1;
-  k.xs_f32 = (epi == EPI_RESID_RELU && p.xsh == nullptr) ? 1 : 0;
-#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF)                                         \
+  const bool res = epi == EPI_RESID_RELU || epi == EPI_RESID_GAP;
+  if (epi == EPI_RESID_GAP) k.out_f32 = 1;
+  k.xs_f32 = (res && p.xsh == nullptr) ? 1 : 0;
+  k.csp = res ? cip_of(p.Cs) : 0;
+  if (res && (!p.wspk || p.Ls != 2 * p.Lout)) return hipErrorInvalidValue;
+  if (epi == EPI_RESID_GAP && (!p.hw || !p.gap_part)) return hipErrorInvalidValue;
+#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS)                                     \
   if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
-      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF)                               \
-    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF>(p, g, st);
+      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF && k.csp == CS)                 \
+    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS>(p, g, st);
   GW_BF16_VARIANTS(GW_LAUNCH)
 #undef GW_LAUNCH
-  (void)find_variant;
   return hipErrorNotSupported;
 }
 

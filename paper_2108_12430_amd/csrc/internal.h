@@ -27,6 +27,7 @@ enum Epi : int {
   EPI_RELU = 3,         // y = max(acc + bias[o], 0)
   EPI_RESID_RELU = 4,   // y = max(acc + bias[o] + shortcut(x_stage)[o], 0)
   EPI_OUT = 5,          // y = acc*scale + shift; noise + causal clean outputs
+  EPI_RESID_GAP = 6,    // as EPI_RESID_RELU, then sum_o hw[o] * y per block (pooling head)
 };
 
 enum Src : int { SRC_DENSE = 0, SRC_RING = 1 };
@@ -45,6 +46,7 @@ struct ConvP {
   const float* w;
   int64_t wso, wsi;
   const uint16_t* wpk;     // packed bf16 weights (BF16 kernels)
+  const uint16_t* wspk;    // packed bf16 1x1 shortcut weights (BF16 residual epilogue)
   const float* bias;
   const float* scale;
   const float* shift;
@@ -54,6 +56,9 @@ struct ConvP {
   const float* ws;         // [Co][Cs]
   const float* bs;         // [Co]
   int Cs, Ls;
+  // pooling head (EPI_RESID_GAP): per-block partial sums of hw[o] * y[o][t]
+  const float* hw;
+  float* gap_part;         // [n][gridDim.x]
   // outputs of EPI_OUT
   float* noise;            // [n][W] or null
   const float* strain;     // packed, or null
@@ -66,6 +71,7 @@ struct ConvP {
 hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool transposed);
+int conv_bf16_col_tile(int Co, bool transposed);  // output columns per block
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool transposed,
                             hipStream_t st);
@@ -81,6 +87,9 @@ hipError_t launch_gather(const void* arena, const Item* items, int n, int C, int
 hipError_t launch_fold_bn(const float* b, const float* gamma, const float* beta, const float* mean,
                           const float* var, float* scale, float* shift, int C, hipStream_t st);
 
+// logits[b] = (sum_k part[b][k]) / L + bias, k < nblk, fixed order
+hipError_t launch_gap_finalize(const float* part, int nblk, const float* bias, float* logits, int n,
+                               int L, hipStream_t st);
 hipError_t launch_gap_linear(const float* a, const float* w, const float* b, float* logits, int n,
                              int C, int L, hipStream_t st);
 

@@ -106,30 +106,27 @@ hipError_t launch_fold_bn(const float* b, const float* gamma, const float* beta,
   return hipGetLastError();
 }
 
-// Classifier head: logit[b] = bias + sum_c w[c] * mean_t a[b][c][t].
-// One block per window; each wavefront owns channels c = wave (mod 4), its
-// lanes stride over time, and the partial sums are combined in a fixed order
-// so the result does not depend on scheduling.
+// Classifier head: logit[b] = bias + (1/L) sum_c sum_t w[c] a[b][c][t]
+// (= bias + w . mean_t a).  One block per window; every lane accumulates a
+// fixed strided subset of the window with independent loads, then the block
+// combines the lane sums in a fixed tree, so the result does not depend on
+// scheduling.
 __global__ __launch_bounds__(256) void gap_linear_kernel(const float* a, const float* w,
                                                          const float* bias, float* logits, int C,
                                                          int L) {
-  __shared__ float gsum[1024];
+  __shared__ float part[256];
   const int b = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float* ab = a + (int64_t)b * C * L;
-  for (int c = wave; c < C; c += 4) {
-    float s = 0.0f;
-    for (int t = lane; t < L; t += 64) s += ab[(int64_t)c * L + t];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) gsum[c] = s;
-  }
+  const int total = C * L;
+  float s = 0.0f;
+  for (int e = threadIdx.x; e < total; e += 256) s = fmaf(w[e / L], ab[e], s);
+  part[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    float acc = 0.0f;
-    const float inv = 1.0f / (float)L;
-    for (int c = 0; c < C; ++c) acc = fmaf(w[c], gsum[c] * inv, acc);
-    logits[b] = acc + bias[0];
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) logits[b] = part[0] / (float)L + bias[0];
 }
 
 hipError_t launch_gap_linear(const float* a, const float* w, const float* b, float* logits, int n,
@@ -179,6 +176,26 @@ __global__ __launch_bounds__(256) void zero_floats_kernel(float* dst, int64_t n)
 hipError_t launch_zero_floats(float* dst, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_floats_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace gw
+
+namespace gw {
+
+__global__ void gap_finalize_kernel(const float* part, int nblk, const float* bias, float* logits, int n,
+                                    int L) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n) return;
+  float s = 0.0f;
+  for (int k = 0; k < nblk; ++k) s += part[(int64_t)b * nblk + k];
+  logits[b] = s / (float)L + bias[0];
+}
+
+hipError_t launch_gap_finalize(const float* part, int nblk, const float* bias, float* logits, int n,
+                               int L, hipStream_t st) {
+  hipLaunchKernelGGL(gap_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, bias, logits,
+                     n, L);
   return hipGetLastError();
 }
 

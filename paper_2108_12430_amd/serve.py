@@ -1,0 +1,338 @@
+"""Continuous-batching request loop for many concurrent streams.
+
+Requests of one stream carry floor(f_s/r) strictly new samples and must be
+applied in order (the state update is sequential, App. B.1), while inference
+on different streams (and on adjacent windows) can run in parallel.  Each
+step of this loop therefore takes at most one pending request per admitted
+stream, groups the requests by (model, channels, window), and issues one
+batched snapshot_update plus one batched forward per group on that group's
+own HIP stream, so different groups overlap on the device.  Requests that
+arrive while earlier steps are still running are admitted into the next step
+(continuous batching); streams are admitted by arena memory: when the pool
+refuses a new stream (GW_ENOMEM) it waits in an admission queue until another
+stream closes.
+
+The loop is written against a small executor interface so that its host
+logic (admission, ordering, grouping, latency accounting) can be exercised
+without a GPU; ``HipExecutor`` is the device implementation and the only one
+this package provides.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Deque, Dict, List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    stream: int
+    samples: np.ndarray            # [C][s] float32, strictly new samples
+    strain: Optional[np.ndarray]   # [s] float32 (DeepClean streams) or None
+    t_arrival: float
+    seq: int = 0
+    t_done: Optional[float] = None
+    result: Any = None             # clean strain [s] (DeepClean) or logit (BBHnet)
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+@dataclass
+class StreamState:
+    sid: int
+    model: str
+    C: int
+    W: int
+    slot: Optional[int] = None
+    pending: Deque[Request] = field(default_factory=collections.deque)
+    next_seq: int = 0
+    done_seq: int = 0
+    closing: bool = False
+
+
+class Server:
+    """Admission, per-stream FIFOs, per-step grouping and completion tracking.
+
+    executor: object with
+      open(model, C, W) -> slot or None (no room)
+      close(slot)
+      launch(model, C, W, items: list[(slot, Request)]) -> handle
+      poll(handle) -> bool             (non-blocking completion check)
+      finish(handle) -> list[result]   (results in item order; handle done)
+    """
+
+    def __init__(self, executor, clock: Callable[[], float] = time.perf_counter, max_inflight: int = 4):
+        self.ex = executor
+        self.clock = clock
+        self.max_inflight = max_inflight
+        self.streams: Dict[int, StreamState] = {}
+        self.admission: Deque[int] = collections.deque()
+        self.inflight: Deque[Tuple[Any, List[Request]]] = collections.deque()
+        self.completed: List[Request] = []
+        self._next_sid = 0
+        self.steps = 0
+
+    # ---- stream lifecycle ------------------------------------------------
+    def open_stream(self, model: str, C: int, W: int) -> int:
+        sid = self._next_sid
+        self._next_sid += 1
+        st = StreamState(sid, model, C, W)
+        self.streams[sid] = st
+        self.admission.append(sid)
+        self._admit()
+        return sid
+
+    def admitted(self, sid: int) -> bool:
+        return self.streams[sid].slot is not None
+
+    def close_stream(self, sid: int) -> None:
+        """Close after the stream's queued requests have completed."""
+        st = self.streams[sid]
+        st.closing = True
+        self._reap_closed()
+
+    def _admit(self) -> None:
+        while self.admission:
+            st = self.streams[self.admission[0]]
+            slot = self.ex.open(st.model, st.C, st.W)
+            if slot is None:
+                break  # FIFO admission: later streams wait behind the head
+            st.slot = slot
+            self.admission.popleft()
+
+    def _reap_closed(self) -> None:
+        freed = False
+        for sid in list(self.streams):
+            st = self.streams[sid]
+            if st.closing and not st.pending and st.done_seq == st.next_seq:
+                if st.slot is not None:
+                    self.ex.close(st.slot)
+                    freed = True
+                elif sid in self.admission:
+                    self.admission.remove(sid)
+                del self.streams[sid]
+        if freed:
+            self._admit()
+
+    # ---- requests ----------------------------------------------------------
+    def submit(self, sid: int, samples: np.ndarray, strain: Optional[np.ndarray] = None,
+               t_arrival: Optional[float] = None) -> Request:
+        st = self.streams[sid]
+        if st.closing:
+            raise ValueError("stream is closing")
+        samples = np.ascontiguousarray(samples, dtype=np.float32)
+        if samples.ndim != 2 or samples.shape[0] != st.C or not (1 <= samples.shape[1] <= st.W):
+            raise ValueError(f"stream {sid} expects [{st.C}][1..{st.W}] samples, got {samples.shape}")
+        if strain is not None:
+            strain = np.ascontiguousarray(strain, dtype=np.float32)
+            if strain.shape != (samples.shape[1],):
+                raise ValueError("strain must hold one value per new sample")
+        r = Request(sid, samples, strain, self.clock() if t_arrival is None else t_arrival, st.next_seq)
+        st.next_seq += 1
+        st.pending.append(r)
+        return r
+
+    def pending(self) -> int:
+        return sum(len(s.pending) for s in self.streams.values())
+
+    # ---- the loop ----------------------------------------------------------
+    def step(self) -> int:
+        """Issue one step (at most one request per admitted stream, grouped by
+        (model, C, W)); returns the number of requests issued."""
+        self.poll()
+        while len(self.inflight) >= self.max_inflight:
+            self._complete_oldest(block=True)
+        groups: Dict[Tuple[str, int, int], List[Tuple[int, Request]]] = collections.OrderedDict()
+        for st in self.streams.values():
+            if st.slot is None or not st.pending:
+                continue
+            r = st.pending.popleft()
+            groups.setdefault((st.model, st.C, st.W), []).append((st.slot, r))
+        n = 0
+        for (model, C, W), items in groups.items():
+            h = self.ex.launch(model, C, W, items)
+            self.inflight.append((h, [r for _, r in items]))
+            n += len(items)
+        if n:
+            self.steps += 1
+        return n
+
+    def poll(self) -> None:
+        """Retire every in-flight group whose work has completed (in order)."""
+        while self.inflight and self.ex.poll(self.inflight[0][0]):
+            self._complete_oldest(block=False)
+
+    def _complete_oldest(self, block: bool) -> None:
+        h, reqs = self.inflight.popleft()
+        res = self.ex.finish(h)
+        t = self.clock()
+        for r, v in zip(reqs, res):
+            r.result = v
+            r.t_done = t
+            st = self.streams.get(r.stream)
+            if st is not None:
+                st.done_seq += 1
+            self.completed.append(r)
+        self._reap_closed()
+
+    def drain(self) -> None:
+        while self.pending() or self.inflight:
+            if not self.step():
+                if self.inflight:
+                    self._complete_oldest(block=True)
+                elif self.pending():
+                    break  # pending requests of streams not yet admitted
+
+    def latency_stats(self) -> Dict[str, float]:
+        lat = np.array([r.latency for r in self.completed if r.latency is not None])
+        if lat.size == 0:
+            return {}
+        return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
+
+
+# ---------------------------------------------------------------------------
+# Device executor
+# ---------------------------------------------------------------------------
+
+class HipExecutor:
+    """Runs each group on the device through the C ABI: one pinned host
+    staging copy of the group's new samples (and strain), one batched
+    snapshot_update, one batched forward (DeepClean: fully-online clean
+    strain; BBHnet: logits) and one copy of the results back, all on the
+    group's own HIP stream, completed by an event.  Staging and output
+    buffers are preallocated per group in a small ring and reused once the
+    work that used them has completed."""
+
+    RING = 6  # per-group buffer sets; must exceed the server's max_inflight
+
+    def __init__(self, models: Dict[str, Any], arena_bytes: int, max_slots: int = 1024, max_items: int = 1024,
+                 precision: int = 1, device: str = "cuda:0"):
+        import torch
+
+        from . import gwstream as gs
+        self.torch = torch
+        self.gs = gs
+        self.dev = torch.device(device)
+        self.models = models
+        self.precision = precision
+        self.pool = gs.Pool(arena_bytes, max_slots=max_slots, max_items=max_items, device=device)
+        self.streams: Dict[Tuple[str, int, int], Any] = {}
+        self.ws: Dict[Tuple[str, int, int], Any] = {}
+        self.ws_n: Dict[Tuple[str, int, int], int] = {}
+        self.bufs: Dict[Tuple[str, int, int], List[Dict[str, Any]]] = {}
+        self.next_buf: Dict[Tuple[str, int, int], int] = {}
+
+    def _stream(self, key):
+        st = self.streams.get(key)
+        if st is None:
+            st = self.streams[key] = self.torch.cuda.Stream(device=self.dev)
+        return st
+
+    def open(self, model, C, W):
+        # the ring's zero fill goes on the stream all of this group's updates
+        # use, so it is ordered before the stream's first request
+        return self.pool.try_open(C, W, stream=self._stream((model, C, W)))
+
+    def close(self, slot):
+        self.pool.close(slot)
+
+    def _ws(self, key, n):
+        """Workspace of a group, allocated on (and only used on) its stream."""
+        model, C, W = key
+        if self.ws_n.get(key, 0) < n:
+            m = self.models[model]
+            nb = m.workspace_bytes(n, W, self.precision)
+            with self.torch.cuda.stream(self._stream(key)):
+                self.ws[key] = self.torch.empty(nb, dtype=self.torch.uint8, device=self.dev)
+            self.ws_n[key] = n
+        return self.ws[key]
+
+    def _buf(self, key, n_f, n_s, n_out):
+        """Next buffer set of a group with room for n_f samples, n_s strain
+        values and n_out outputs (grown by doubling when too small)."""
+        torch = self.torch
+        ring = self.bufs.setdefault(key, [None] * self.RING)
+        k = self.next_buf.get(key, 0)
+        self.next_buf[key] = (k + 1) % self.RING
+        b = ring[k]
+        if b is not None and b["ev"] is not None:
+            b["ev"].synchronize()
+        if b is None or b["cap"][0] < n_f or b["cap"][1] < n_s or b["cap"][2] < n_out:
+            cap = [max(n_f, 1), max(n_s, 1), max(n_out, 1)]
+            if b is not None:
+                cap = [max(c, 2 * o) if c > o else o for c, o in zip(cap, b["cap"])]
+            with torch.cuda.stream(self._stream(key)):
+                b = {"cap": cap,
+                     "h_x": torch.empty(cap[0], dtype=torch.float32, pin_memory=True),
+                     "h_s": torch.empty(cap[1], dtype=torch.float32, pin_memory=True),
+                     "h_o": torch.empty(cap[2], dtype=torch.float32, pin_memory=True),
+                     "d_x": torch.empty(cap[0], dtype=torch.float32, device=self.dev),
+                     "d_s": torch.empty(cap[1], dtype=torch.float32, device=self.dev),
+                     "d_o": torch.empty(cap[2], dtype=torch.float32, device=self.dev)}
+            ring[k] = b
+        b["ev"] = None
+        return b
+
+    def launch(self, model, C, W, items):
+        torch = self.torch
+        key = (model, C, W)
+        st = self._stream(key)
+        m = self.models[model]
+        is_dc = isinstance(m, self.gs.DeepClean)
+        slots = [s for s, _ in items]
+        strides = np.fromiter((r.samples.shape[1] for _, r in items), dtype=np.int64, count=len(items))
+        sizes = C * strides
+        offsets = np.zeros(len(items), np.int64)
+        np.cumsum(sizes[:-1], out=offsets[1:])
+        n_f = int(sizes.sum())
+        s_tot = int(strides.sum())
+        n_out = s_tot if is_dc else len(items)
+        b = self._buf(key, n_f, s_tot if is_dc else 0, n_out)
+        hv = b["h_x"].numpy()
+        for (_, r), o, sz in zip(items, offsets, sizes):
+            hv[o:o + sz] = r.samples.reshape(-1)
+        if is_dc:
+            sv = b["h_s"].numpy()
+            o = 0
+            for (_, r), s in zip(items, strides):
+                sv[o:o + s] = r.strain if r.strain is not None else 0.0
+                o += s
+        ws = self._ws(key, len(items))
+        with torch.cuda.stream(st):
+            dx = b["d_x"][:n_f]
+            dx.copy_(b["h_x"][:n_f], non_blocking=True)
+            self.pool.update(slots, strides, dx, offsets, stream=st)
+            out = b["d_o"][:n_out]
+            if is_dc:
+                ds = b["d_s"][:s_tot]
+                ds.copy_(b["h_s"][:s_tot], non_blocking=True)
+                m.forward(pool=self.pool, slots=slots, W=W, strides=strides, strain=ds, clean=out,
+                          precision=self.precision, ws=ws, stream=st)
+            else:
+                m.forward(pool=self.pool, slots=slots, W=W, logits=out, precision=self.precision, ws=ws,
+                          stream=st)
+            b["h_o"][:n_out].copy_(out, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        b["ev"] = ev
+        return {"ev": ev, "buf": b, "n_out": n_out, "strides": strides, "dc": is_dc}
+
+    def poll(self, h):
+        return h["ev"].query()
+
+    def finish(self, h):
+        h["ev"].synchronize()
+        out = h["buf"]["h_o"].numpy()[:h["n_out"]].copy()
+        if not h["dc"]:
+            return list(out)
+        res, o = [], 0
+        for s in h["strides"]:
+            res.append(out[o:o + s])
+            o += s
+        return res

@@ -285,3 +285,36 @@ def test_streaming_bf16_bitwise(dc):
     check = [0, 127, 128, N - 1]
     xs = np.stack([ref.snapshot_after(wit, (u + 1) * s, W) for u in check])
     assert rel(noise_all[check].cpu().numpy(), ref.deepclean_forward(params, xs, layers)) <= BF16_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [(gs.FP32, FP32_TOL), (gs.BF16, BF16_TOL)])
+def test_pool_batch_mixed_strides(dc, prec, tol):
+    """One batched call over several streams with different strides: every
+    item's noise window and packed clean block match the oracle."""
+    m, params, layers = dc
+    W, strides = 4096, [256, 512, 128, 1024]
+    n = len(strides)
+    pool = gs.Pool(64 << 20, max_slots=8, max_items=8)
+    slots = [pool.open(21, W) for _ in range(n)]
+    data = [synth.witness_stream(300 + i, 6000) for i in range(n)]
+    pos = [0] * n
+    for k in range(3):
+        blocks = [np.ascontiguousarray(data[i][0][:, pos[i]:pos[i] + strides[i]]).reshape(-1) for i in range(n)]
+        offs = np.cumsum([0] + [21 * s for s in strides[:-1]])
+        pool.update(slots, strides, torch.from_numpy(np.concatenate(blocks)).to(DEV), offs)
+        pos = [p + s for p, s in zip(pos, strides)]
+    strain = np.concatenate([data[i][1][pos[i] - strides[i]:pos[i]] for i in range(n)])
+    clean = torch.empty(sum(strides), device=DEV)
+    noise = torch.empty((n, W), device=DEV)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, strain=torch.from_numpy(strain).to(DEV),
+              clean=clean, noise=noise, precision=prec)
+    torch.cuda.synchronize()
+    xs = np.stack([ref.snapshot_after(data[i][0], pos[i], W) for i in range(n)])
+    en = ref.deepclean_forward(params, xs, layers)
+    assert rel(noise.cpu().numpy(), en) <= tol
+    o = 0
+    got = clean.cpu().numpy()
+    for i, s in enumerate(strides):
+        _, ec = ref.causal_clean(en[i:i + 1], data[i][1][None, pos[i] - s:pos[i]])
+        assert rel(got[o:o + s], ec[0]) <= tol
+        o += s
