@@ -137,6 +137,60 @@ def cpu_baseline(dc_s, bb_s, budget_s=12.0):
                       f"full-window recompute per request), {dt:.1f} s"}
 
 
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the summary is missing or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_serving_mix_bf16.json")
+    try:
+        d = json.load(open(path))
+        src = open(os.path.join(ROOT, d["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
+def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True):
+    """One DeepClean training step = batch-statistics forward, band-passed
+    MSE (55-65 Hz), hand-written backward (FP32); the optimizer update is
+    outside the library and not timed."""
+    import torch
+
+    from paper_2108_12430_amd import gwstream as gs
+    from paper_2108_12430_amd import synth
+    params = torch.from_numpy(synth.deepclean_params(0)).to(dev)
+    m = gs.DeepClean(params, synth.deepclean_layers())
+    wit, strain = synth.witness_stream(4, 4 * W)
+    x = torch.from_numpy(np.ascontiguousarray(np.tile(wit.reshape(DC_C, 4, W).transpose(1, 0, 2), (B // 4, 1, 1))))
+    x = x.to(dev)
+    st = torch.from_numpy(np.ascontiguousarray(np.tile(strain.reshape(4, W), (B // 4, 1)))).to(dev)
+    flags = gs.TRAIN | (gs.RECOMPUTE if recompute else 0)
+    noise = torch.empty((B, W), device=dev)
+    ws = torch.empty(m.workspace_bytes(B, W, gs.FP32, flags), dtype=torch.uint8, device=dev)
+    scratch = torch.empty(m.backward_scratch_bytes(B, W, flags), dtype=torch.uint8, device=dev)
+    dp = torch.empty_like(params)
+
+    def one():
+        m.forward(x=x, noise=noise, flags=flags, ws=ws)
+        loss, dn = gs.bandpass_mse(st, noise, float(DC_FS), 55.0, 65.0)
+        m.backward(x, dn, ws, dp, flags=flags, scratch=scratch)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"batch": B, "window": W, "ms_per_step": 1e3 * dt, "samples_per_s": B * W / dt, "dtype": "f32",
+            "recompute": recompute, "workspace_MB": (ws.numel() + scratch.numel()) / 1e6}
+
+
 def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
     """Serving loop (continuous batching, host requests staged through pinned
     memory, so PCIe-inclusive) on the same 256-stream mix: a closed-loop run
@@ -240,6 +294,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -365,6 +421,42 @@ def main():
         log(f"bench: copy calibration {args.copy_calibration} MiB x 3")
         del a, c
 
+    # fully-online output only (GW_CAUSAL): the DeepClean streams compute just
+    # the band of each window that their newest samples depend on
+    def step_band(k):
+        pool.update(slots, strides, staged[k], offsets)
+        dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
+                   precision=prec, ws=ws_dc, flags=gs.CAUSAL)
+        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb)
+
+    band = None
+    if not args.no_band:
+        kb = 0
+        for _ in range(args.warmup):
+            step_band(kb % n_steps_total)
+            kb += 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_band(kb % n_steps_total)
+            kb += 1
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        latb = []
+        for _ in range(args.lat_steps):
+            t1 = time.perf_counter()
+            step_band(kb % n_steps_total)
+            torch.cuda.synchronize()
+            latb.append(1e3 * (time.perf_counter() - t1))
+            kb += 1
+        latb = np.array(latb) if latb else np.zeros(1)
+        band = {"value": step_samples * args.steps / dtb, "unit": "samples/s", "ms_per_step": 1e3 * dtb / args.steps,
+                "p50_ms": float(np.percentile(latb, 50)), "p99_ms": float(np.percentile(latb, 99)),
+                "note": "DeepClean computes only the receptive-field band of each window its newest samples need; "
+                        "clean output bitwise equal to the full-window recompute"}
+        log(f"bench: causal band {band['value']:.4g} samples/s, {band['ms_per_step']:.3f} ms/step, "
+            f"p99 {band['p99_ms']:.3f} ms")
+
     roof = None
     if not args.no_roofline:
         gs.profile_begin()
@@ -385,7 +477,7 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
+        roof["traffic"] = traffic_for(name)
         roof["kernel"] = name
         roof["avg_us"] = avg_s * 1e6
         roof["algorithmic_flops"] = flops
@@ -429,6 +521,11 @@ def main():
                  "dtype": "f32", "batching": "one stream per launch"}
         log(f"bench: fp32 plain {plain['value']:.4g} samples/s, p99 {plain['p99_ms']:.3f} ms")
 
+    training = None
+    if not args.no_train:
+        training = train_bench(dev)
+        log(f"bench: training step {training}")
+
     serving = None
     if not args.no_serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
@@ -450,7 +547,8 @@ def main():
                    "channel_samples_per_step": int(DC_C * dc_s.sum() + BB_C * bb_s.sum())},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
-        "fp32_plain": plain, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
+        "fp32_plain": plain, "causal_band": band, "serving": serving, "training": training, "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

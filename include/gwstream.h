@@ -67,6 +67,12 @@ extern "C" {
                               save what deepclean_backward needs into ws      */
 #define GW_RECOMPUTE 2u    /* with GW_TRAIN: save only checkpoints, recompute
                               the rest in deepclean_backward                   */
+#define GW_CAUSAL 4u       /* deepclean_forward inference: compute only what the
+                              fully-online output needs (the newest s samples
+                              depend on a band of about s + 93 input samples at
+                              the end of the window, the network's receptive
+                              field); clean is bitwise equal to the full-window
+                              result; noise must be NULL                      */
 
 #define GW_LAYER_CONV 0
 #define GW_LAYER_CONVT 1
@@ -194,7 +200,11 @@ int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t pre
  *          newest strain samples of each item).
  * precision GW_FP32 or GW_BF16.  flags: 0 (inference, running statistics),
  * GW_TRAIN (batch statistics over n*time per channel; requires x),
- * GW_TRAIN|GW_RECOMPUTE.  Returns GW_EINVAL if ws_bytes is too small.
+ * GW_TRAIN|GW_RECOMPUTE, or GW_CAUSAL (inference, clean output only; the
+ * band is chosen from the largest stride and aligned to the network's total
+ * stride so every layer's sample grid coincides with the full window's).
+ * Returns GW_EINVAL if ws_bytes is too small (the size deepclean_workspace
+ * returns for the same n, W, precision and flags always suffices).
  * W must be a multiple of 16 (four stride-2 stages).
  */
 int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, const float* x,
@@ -211,7 +221,9 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
  * accumulated; running-statistics entries get 0.  With GW_RECOMPUTE the
  * activations are recomputed from checkpoints; the result is bitwise equal
  * to the stored-activation path.  `scratch` needs deepclean_backward_scratch
- * bytes.  All reductions have a fixed order (deterministic).
+ * bytes.  All reductions have a fixed order (deterministic).  precision must
+ * equal the forward's: GW_BF16 runs the forward (and recomputed) convolutions
+ * on BF16 matrix cores with FP32 activations, statistics and gradients.
  */
 int deepclean_backward_scratch(const gw_model* model, int32_t n, int32_t W, uint32_t flags,
                                size_t* bytes);

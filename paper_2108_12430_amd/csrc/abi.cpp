@@ -572,6 +572,50 @@ int dc_lengths(const gw_model* m, int W, std::vector<int>& lin, std::vector<int>
   return GW_OK;
 }
 
+// Start `a` of the input band [a, W) that the newest s outputs depend on:
+// propagate the needed index range back through the layers, then align `a`
+// to the network's total stride so every layer's sample grid in the band
+// coincides with the full window's, and check that at every layer the band
+// still contains every needed position.  Returns 0 when no shorter band works.
+int causal_band_start(const gw_model* m, int W, int s) {
+  std::vector<int> lin, lout;
+  if (dc_lengths(m, W, lin, lout) != GW_OK || s >= W) return 0;
+  const int L = (int)m->layers.size();
+  std::vector<int64_t> need(L);
+  int64_t lo = W - s, hi = W - 1;
+  for (int l = L - 1; l >= 0; --l) {
+    const LayerD& ly = m->layers[l];
+    int64_t a, b;
+    if (ly.type == GW_LAYER_CONV) {
+      a = (int64_t)ly.s * lo - ly.p;
+      b = (int64_t)ly.s * hi - ly.p + ly.k - 1;
+    } else {
+      const int64_t num = lo + ly.p - ly.k + 1;
+      a = num >= 0 ? (num + ly.s - 1) / ly.s : -((-num) / ly.s);
+      const int64_t nh = hi + ly.p;
+      b = nh >= 0 ? nh / ly.s : -((-nh + ly.s - 1) / ly.s);
+    }
+    lo = std::max<int64_t>(a, 0);
+    hi = std::min<int64_t>(b, lin[l] - 1);
+    need[l] = lo;
+  }
+  int64_t D = 1;
+  for (auto& ly : m->layers)
+    if (ly.type == GW_LAYER_CONV) D *= ly.s;
+  for (int64_t a = need[0] / D * D; a > 0; a -= D) {
+    std::vector<int> li, lo2;
+    if (dc_lengths(m, (int)(W - a), li, lo2) != GW_OK) continue;
+    bool ok = true;
+    for (int l = 0; l < L && ok; ++l) {
+      if ((a * lin[l]) % W) ok = false;                 // grids must coincide
+      else if (a * lin[l] / W > need[l]) ok = false;     // band must cover the need
+      else if (li[l] != lin[l] - a * lin[l] / W) ok = false;
+    }
+    if (ok) return (int)a;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" int gw_model_n_params(int32_t kind, const int32_t* desc, int32_t desc_len, int64_t* n) {
@@ -763,20 +807,35 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
   if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
   if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
-  if (flags & ~(GW_TRAIN | GW_RECOMPUTE)) return fail(GW_EINVAL, "bad flags");
+  if (flags & ~(GW_TRAIN | GW_RECOMPUTE | GW_CAUSAL)) return fail(GW_EINVAL, "bad flags");
+  if ((flags & GW_CAUSAL) && (flags & GW_TRAIN)) return fail(GW_EINVAL, "GW_CAUSAL is for inference");
+  if ((flags & GW_CAUSAL) && (!clean || noise))
+    return fail(GW_EINVAL, "GW_CAUSAL computes only the clean output (noise must be NULL)");
   if ((flags & GW_RECOMPUTE) && !(flags & GW_TRAIN)) return fail(GW_EINVAL, "GW_RECOMPUTE needs GW_TRAIN");
   if ((flags & GW_TRAIN) && !x) return fail(GW_EINVAL, "training forward needs dense input x");
-  if ((flags & GW_TRAIN) && precision != GW_FP32) return fail(GW_EUNSUPPORTED, "training path is FP32");
+
   if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
   if (clean && (!strides || !strain)) return fail(GW_EINVAL, "clean output needs strides and strain");
   if (!ws) return fail(GW_EINVAL, "null workspace");
+  {
+    std::vector<int> l0, l1;
+    CHK(dc_lengths(m, W, l0, l1));
+  }
+  // GW_CAUSAL: run the layers on the band [a, W) only
+  int a_band = 0;
+  if (flags & GW_CAUSAL) {
+    int smax = 1;
+    for (int i = 0; i < n; ++i) smax = std::max(smax, strides[i]);
+    a_band = causal_band_start(m, W, smax);
+  }
+  const int Wb = W - a_band;
   DcWs w;
-  CHK(dc_ws_layout(m, n, W, precision, flags, w));
+  CHK(dc_ws_layout(m, n, Wb, precision, flags & ~GW_CAUSAL, w));
   if (ws_bytes < w.total)
     return fail(GW_EINVAL, "workspace too small: need " + std::to_string(w.total) + " bytes");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GW_EINVAL, "workspace not 256-byte aligned");
   std::vector<int> lin, lout;
-  CHK(dc_lengths(m, W, lin, lout));
+  CHK(dc_lengths(m, Wb, lin, lout));
 
   // item table: ring addresses (pool input) and stride/offset of the clean block
   const bool need_items = pool || clean;
@@ -796,7 +855,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
         if (s.C != m->c_in || s.W != W) return fail(GW_EINVAL, "slot C/W does not match the model and W");
         it.ring = pool->ring_elem(s);
         it.shadow = pool->shadow_elem(s);
-        it.head = s.head;
+        it.head = (s.head + a_band) % s.W;  // oldest sample of the band
         it.C = s.C;
         it.W = s.W;
       }
@@ -822,13 +881,14 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   const int L = (int)m->layers.size();
   const void* arena = pool ? pool->arena : nullptr;
   if (!(flags & GW_TRAIN)) {
-    const float* in = x;
+    const float* in = x ? x + a_band : nullptr;
     for (int l = 0; l < L; ++l) {
       const LayerD& ly = m->layers[l];
       gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
       p.items = dev_items;
       p.arena = arena;
       p.x = in;
+      if (l == 0 && x) p.ldx = W;  // band rows inside full-length input rows
       const int src = (l == 0 && pool) ? gw::SRC_RING : gw::SRC_DENSE;
       int epi;
       if (l == L - 1) {
@@ -860,7 +920,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       p.noise = noise;
       p.clean = clean;
       p.strain = strain;
-      LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_OUT, gw::SRC_DENSE, GW_FP32, st));
+      LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_OUT, gw::SRC_DENSE, precision, st));
       break;
     }
     float* z = reinterpret_cast<float*>(wsb + (w.ckpt >= 0 ? w.ztmp : (ly.bn ? w.z[l] : w.a[l])));
@@ -873,7 +933,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       a = reinterpret_cast<float*>(wsb + w.atmp[l & 1]);
     if (!ly.bn) z = a;
     p.y = z;
-    LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+    LAUNCH(nm("dc_train_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, precision, st));
     if (ly.bn) {
       float* mean = reinterpret_cast<float*>(wsb + w.mean[l]);
       float* invstd = reinterpret_cast<float*>(wsb + w.invstd[l]);
@@ -979,7 +1039,8 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
   if (!x || !dnoise || !saved || !dparams || !scratch) return fail(GW_EINVAL, "null argument");
   if (!(flags & GW_TRAIN) || (flags & ~(GW_TRAIN | GW_RECOMPUTE)))
     return fail(GW_EINVAL, "flags must be GW_TRAIN or GW_TRAIN|GW_RECOMPUTE (as in the forward)");
-  if (precision != GW_FP32) return fail(GW_EUNSUPPORTED, "training path is FP32");
+  if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
+  if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
   DcWs w;
   CHK(dc_ws_layout(m, n, W, precision, flags, w));
   BwWs b;
@@ -1014,7 +1075,7 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
       float* a = scf(b.a[l]);
       float* z = ly.bn ? scf(b.z[l]) : a;
       p.y = z;
-      LAUNCH(nm("dc_recompute_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, GW_FP32, st));
+      LAUNCH(nm("dc_recompute_conv", "L", l), st, run_conv(p, ly, gw::EPI_BIAS, gw::SRC_DENSE, precision, st));
       if (ly.bn)
         LAUNCH(nm("bn_apply", "L", l), st, gw::launch_bn_apply_tanh(z, savedf(w.mean[l]), savedf(w.invstd[l]), m->params + ly.g,
                                         m->params + ly.be, a, n, ly.co, lout[l], st));

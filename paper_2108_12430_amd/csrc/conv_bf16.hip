@@ -143,95 +143,124 @@ hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k
 // its 8 positions with one 16-byte load (32 bytes for FP32 input) when the
 // chunk is aligned and inside the signal, element by element otherwise.
 // ---------------------------------------------------------------------------
-template <int CIP, int ROWS, int RS, int IN>
-__device__ __forceinline__ void stage_input(uint16_t* tile, const ConvP& p, int b, int q0) {
-  // upper bound of (channel, chunk) items per thread; all of a thread's
-  // global loads are issued before any LDS store so they are in flight together
-  constexpr int NCHMAX = (ROWS + 7 + 7) / 8;
-  constexpr int ITEMS = (NCHMAX * CIP + 255) / 256;
-  const int Ci = p.Ci, Lin = p.Lin;
+template <int CIP, int ROWS, int IN>
+struct InRaw {
+  static constexpr int NCHMAX = (ROWS + 7 + 7) / 8;          // 8-position chunks per channel
+  static constexpr int ITEMS = (NCHMAX * CIP + 255) / 256;    // (channel, chunk) items per thread
+  static constexpr int NV = IN == IN_F32 ? 2 : 1;
+  uint4 v[ITEMS][NV];  // raw 16-byte pieces (two for FP32 input)
+  uint32_t f32mask;    // items whose v[it][0..1] still hold 8 FP32 values
+};
+
+// Issue the global loads of one tile's input window into registers.  Tile
+// row r holds input position q0 + r for every channel; work items are
+// (channel, 8-position chunk) with the channel varying fastest across lanes.
+// Each item is one 16-byte load (two for FP32 input) when the chunk is
+// aligned and inside the signal, element by element otherwise.
+template <int CIP, int ROWS, int IN>
+__device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN>& R, const ConvP& p, int b, int q0) {
+  constexpr int ITEMS = InRaw<CIP, ROWS, IN>::ITEMS;
+  const int Ci = p.Ci, Lin = p.Lin;  // positions q in [0, Lin) exist; others are zero padding
   const int qa = q0 - (((q0 % 8) + 8) % 8);  // floor to a multiple of 8
   const int nch = (q0 + ROWS - qa + 7) / 8;
   int head = 0;
+  int ld = p.ldx ? p.ldx : Lin;  // row stride; a ring wraps at its length
   const uint16_t* hbase = nullptr;
   const float* fbase = nullptr;
-  bool vec = (Lin & 7) == 0;
+  bool vec;
   if (IN == IN_RING) {
     const Item& it = p.items[b];
     head = it.head;
+    ld = it.W;
     hbase = reinterpret_cast<const uint16_t*>(p.arena) + it.shadow;
-    vec = vec && (head & 7) == 0 && (it.shadow & 7) == 0;
+    vec = (ld & 7) == 0 && (head & 7) == 0 && (it.shadow & 7) == 0;
   } else if (IN == IN_BF16) {
-    hbase = p.xh + (int64_t)b * Ci * Lin;
-    vec = vec && (reinterpret_cast<uintptr_t>(p.xh) & 15) == 0;
+    hbase = p.xh + (int64_t)b * Ci * ld;
+    vec = (ld & 7) == 0 && (reinterpret_cast<uintptr_t>(p.xh) & 15) == 0;
   } else {
-    fbase = p.x + (int64_t)b * Ci * Lin;
-    vec = vec && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
+    fbase = p.x + (int64_t)b * Ci * ld;
+    vec = (ld & 7) == 0 && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
   }
-  uint4 raw[ITEMS];
+  R.f32mask = 0;
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const int e = threadIdx.x + 256 * it;
     const int i = e % CIP, ch = e / CIP;
     const int qc = qa + 8 * ch;
-    uint16_t v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = 0;
+    R.v[it][0] = make_uint4(0, 0, 0, 0);
     if (ch < nch && i < Ci) {
       if (vec && qc >= 0 && qc + 8 <= Lin) {
         if (IN == IN_F32) {
-          const float4* src = reinterpret_cast<const float4*>(fbase + (int64_t)i * Lin + qc);
-          const float4 a = src[0], c = src[1];
-          v[0] = bf16_rne(a.x); v[1] = bf16_rne(a.y); v[2] = bf16_rne(a.z); v[3] = bf16_rne(a.w);
-          v[4] = bf16_rne(c.x); v[5] = bf16_rne(c.y); v[6] = bf16_rne(c.z); v[7] = bf16_rne(c.w);
+          const uint4* src = reinterpret_cast<const uint4*>(fbase + (int64_t)i * ld + qc);
+          R.v[it][0] = src[0];
+          R.v[it][R.NV - 1] = src[1];
+          R.f32mask |= 1u << it;
         } else {
           int ph = qc;
           if (IN == IN_RING) {
             ph = head + qc;
-            if (ph >= Lin) ph -= Lin;
+            if (ph >= ld) ph -= ld;
           }
-          const uint4 u = *reinterpret_cast<const uint4*>(hbase + (int64_t)i * Lin + ph);
-          raw[it] = u;
-          continue;
+          R.v[it][0] = *reinterpret_cast<const uint4*>(hbase + (int64_t)i * ld + ph);
         }
       } else {
+        uint16_t v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int q = qc + k;
+          v[k] = 0;
           if (q >= 0 && q < Lin) {
             if (IN == IN_F32) {
-              v[k] = bf16_rne(fbase[(int64_t)i * Lin + q]);
+              v[k] = bf16_rne(fbase[(int64_t)i * ld + q]);
             } else {
               int ph = q;
               if (IN == IN_RING) {
                 ph = head + q;
-                if (ph >= Lin) ph -= Lin;
+                if (ph >= ld) ph -= ld;
               }
-              v[k] = hbase[(int64_t)i * Lin + ph];
+              v[k] = hbase[(int64_t)i * ld + ph];
             }
           }
         }
+        R.v[it][0] = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                                (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
       }
     }
-    raw[it].x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-    raw[it].y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-    raw[it].z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
-    raw[it].w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
   }
+}
+
+// Write a loaded tile into LDS ([row][channel], row stride RS) plus the zero
+// row used by padded K entries.
+template <int CIP, int ROWS, int RS, int IN>
+__device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROWS, IN>& R, int q0) {
+  constexpr int ITEMS = InRaw<CIP, ROWS, IN>::ITEMS;
+  const int qa = q0 - (((q0 % 8) + 8) % 8);
+  const int nch = (q0 + ROWS - qa + 7) / 8;
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const int e = threadIdx.x + 256 * it;
     const int i = e % CIP, ch = e / CIP;
     if (ch >= nch) continue;
+    uint16_t v[8];
+    if (IN == IN_F32 && (R.f32mask & (1u << it))) {
+      const uint4 a = R.v[it][0], c = R.v[it][R.NV - 1];
+      v[0] = bf16_rne(__uint_as_float(a.x)); v[1] = bf16_rne(__uint_as_float(a.y));
+      v[2] = bf16_rne(__uint_as_float(a.z)); v[3] = bf16_rne(__uint_as_float(a.w));
+      v[4] = bf16_rne(__uint_as_float(c.x)); v[5] = bf16_rne(__uint_as_float(c.y));
+      v[6] = bf16_rne(__uint_as_float(c.z)); v[7] = bf16_rne(__uint_as_float(c.w));
+    } else {
+      const uint4 u = R.v[it][0];
+      v[0] = u.x & 0xffff; v[1] = u.x >> 16; v[2] = u.y & 0xffff; v[3] = u.y >> 16;
+      v[4] = u.z & 0xffff; v[5] = u.z >> 16; v[6] = u.w & 0xffff; v[7] = u.w >> 16;
+    }
     const int r0 = qa + 8 * ch - q0;
-    const uint32_t w[4] = {raw[it].x, raw[it].y, raw[it].z, raw[it].w};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int r = r0 + k;
-      if (r >= 0 && r < ROWS) tile[r * RS + i] = (uint16_t)(w[k >> 1] >> (16 * (k & 1)));
+      if (r >= 0 && r < ROWS) tile[r * RS + i] = v[k];
     }
   }
-  for (int e = threadIdx.x; e < RS; e += 256) tile[ROWS * RS + e] = 0;  // zero row for padded K
+  for (int e = threadIdx.x; e < RS; e += 256) tile[ROWS * RS + e] = 0;
 }
 
 // Shortcut tile for the residual stage: row c holds the stage input at
@@ -272,10 +301,14 @@ __device__ __forceinline__ void stage_shortcut(uint16_t* xt, const ConvP& p, int
 }
 
 // ---------------------------------------------------------------------------
-// The convolution kernel.  Block = 4 waves; the block owns TN = 64*NTW
-// consecutive columns of one window and all output channels.  With CSP > 0
-// (residual stage) the 1x1 stride-2 shortcut of the stage input is added to
-// the same accumulators as extra K steps.
+// The convolution kernel.  Block = 4 waves; a tile = TN = 64*NTW consecutive
+// output columns of one window and all output channels.  Blocks are
+// persistent: block k processes tiles k, k + gridDim.x, ...; the global loads
+// of the next tile's input are issued before the current tile's matrix work,
+// so HBM latency overlaps computation.  Weights (when they fit) and the
+// epilogue's per-channel constants stay in registers for all tiles.  With
+// CSP > 0 (residual stage) the 1x1 stride-2 shortcut of the stage input is
+// added to the same accumulators as extra K steps.
 // ---------------------------------------------------------------------------
 template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32,
           int CSP>
@@ -286,145 +319,205 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   constexpr int KS = (KT * CIP + 31) / 32;
   constexpr int RSX = CSP + 8;
   constexpr int KS2 = (CSP + 31) / 32;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[(ROWS + 1) * RS];
+  constexpr int NFRAG = NPH * MT * KS;
+  constexpr int TNO = NPH * TN;
+  constexpr bool OTILE = EPI != EPI_OUT && EPI != EPI_RESID_GAP && !OUT_F32;
+  // the input tile's LDS is reused for the BF16 output tile [C_out][NPH*TN]
+  constexpr int TILE = (ROWS + 1) * RS > 16 * MT * TNO ? (ROWS + 1) * RS : 16 * MT * TNO;
+  // weights staged in LDS once per block when they fit beside the tile; only
+  // then is the next tile prefetched (LDS reads do not wait on global loads)
+  constexpr bool ALDS = 2 * TILE + NFRAG * 1024 <= 80 * 1024;
+  __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
   __shared__ __attribute__((aligned(16))) uint16_t xt[CSP > 0 ? (TN + 1) * RSX : 8];
+  __shared__ __attribute__((aligned(16))) uint4 alds[ALDS ? NFRAG * 64 : 1];
+  __shared__ float cst[2][16 * MT];
+  __shared__ float wsum[4];
 
-  const int b = blockIdx.y;
-  const int col0 = blockIdx.x * TN;
-  stage_input<CIP, ROWS, RS, IN>(tile, p, b, SC * col0 - padc);
-  if (CSP > 0) stage_shortcut<CSP, TN, RSX, XS_F32>(xt, p, b, col0);
-  __syncthreads();
-
+  const int tiles_per = (ncol + TN - 1) / TN;
+  const int total = tiles_per * p.n;
+  if ((int)blockIdx.x >= total) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lg = lane >> 4;
   const uint4* wp = reinterpret_cast<const uint4*>(p.wpk);
 
-  f32x4 acc[NTW][NPH][MT];
-#pragma unroll
-  for (int nt = 0; nt < NTW; ++nt)
-#pragma unroll
-    for (int ph = 0; ph < NPH; ++ph)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (ALDS)
+    for (int e = threadIdx.x; e < (ALDS ? NFRAG * 64 : 0); e += 256) alds[e] = wp[e];
+  // per-channel epilogue constants: cst[0] multiplies, cst[1] adds
+  for (int o = threadIdx.x; o < 16 * MT; o += 256) {
+    const int oc = min(o, p.Co - 1);
+    float a = 0.f, c = 0.f;
+    if (EPI == EPI_AFFINE || EPI == EPI_OUT || EPI == EPI_AFFINE_TANH) {
+      a = p.scale[oc];
+      c = p.shift[oc];
+    } else if (EPI == EPI_RELU || EPI == EPI_BIAS) {
+      c = p.bias ? p.bias[oc] : 0.f;
+    } else {
+      c = p.bias[oc] + p.bs[oc];
+      if (EPI == EPI_RESID_GAP) a = p.hw[oc];
+    }
+    cst[0][o] = a;
+    cst[1][o] = c;
+  }
 
-  for (int ks = 0; ks < KS; ++ks) {
-    const int kappa = 32 * ks + 8 * lg;
-    const int jj = kappa / CIP, i0 = kappa - jj * CIP;
-    uint4 af[NPH][MT];
+  InRaw<CIP, ROWS, IN> raw;
+  {
+    const int t = blockIdx.x;
+    load_input<CIP, ROWS, IN>(raw, p, t / tiles_per, SC * ((t % tiles_per) * TN) - padc);
+  }
+  // ALDS: persistent loop over tiles with prefetch; otherwise one tile per block
+  const int tstep = ALDS ? (int)gridDim.x : total;
+  for (int t = blockIdx.x; t < total; t += tstep) {
+    const int b = t / tiles_per;
+    const int col0 = (t % tiles_per) * TN;
+    store_input<CIP, ROWS, RS, IN>(tile, raw, SC * col0 - padc);
+    if (CSP > 0) stage_shortcut<CSP, TN, RSX, XS_F32>(xt, p, b, col0);
+    __syncthreads();
+    if (ALDS) {
+      const int tn = t + tstep;
+      if (tn < total) load_input<CIP, ROWS, IN>(raw, p, tn / tiles_per, SC * ((tn % tiles_per) * TN) - padc);
+    }
+
+    f32x4 acc[NTW][NPH][MT];
 #pragma unroll
-    for (int ph = 0; ph < NPH; ++ph)
+    for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) af[ph][mt] = wp[((ph * MT + mt) * KS + ks) * 64 + lane];
+      for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) {
-      const int c = (wave * NTW + nt) * 16 + lc;
-      const int row = (jj < KT) ? SC * c + jj : ROWS;
-      const uint4 bv = *reinterpret_cast<const uint4*>(&tile[row * RS + i0]);
-      const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
+        for (int mt = 0; mt < MT; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kappa = 32 * ks + 8 * lg;
+      const int jj = kappa / CIP, i0 = kappa - jj * CIP;
+      uint4 af[NPH][MT];
 #pragma unroll
       for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
-    }
-  }
-  if (CSP > 0) {
-    const uint4* sp = reinterpret_cast<const uint4*>(p.wspk);
-    for (int ks = 0; ks < KS2; ++ks) {
-      const int kappa = 32 * ks + 8 * lg;
-      uint4 af[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) af[mt] = sp[(mt * KS2 + ks) * 64 + lane];
+          af[ph][mt] = ALDS ? alds[ALDS ? ((ph * MT + mt) * KS + ks) * 64 + lane : 0]
+                            : wp[((ph * MT + mt) * KS + ks) * 64 + lane];
 #pragma unroll
       for (int nt = 0; nt < NTW; ++nt) {
         const int c = (wave * NTW + nt) * 16 + lc;
-        const int row = kappa < CSP ? c : TN;
-        const uint4 bv = *reinterpret_cast<const uint4*>(&xt[row * RSX + (kappa < CSP ? kappa : 0)]);
+        const int row = (jj < KT) ? SC * c + jj : ROWS;
+        const uint4 bv = *reinterpret_cast<const uint4*>(&tile[row * RS + i0]);
         const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          acc[nt][0][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[mt]), bb,
-                                                                   acc[nt][0][mt], 0, 0, 0);
+        for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
       }
     }
-  }
-
-  // ---- epilogue
-  float gsum = 0.0f;  // EPI_RESID_GAP: this lane's share of sum_o hw[o] y[o][t]
+    if (CSP > 0) {
+      const uint4* sp = reinterpret_cast<const uint4*>(p.wspk);
+      for (int ks = 0; ks < KS2; ++ks) {
+        const int kappa = 32 * ks + 8 * lg;
+        uint4 af[MT];
 #pragma unroll
-  for (int nt = 0; nt < NTW; ++nt) {
-    const int col = col0 + (wave * NTW + nt) * 16 + lc;
-    if (col >= ncol) continue;
+        for (int mt = 0; mt < MT; ++mt) af[mt] = sp[(mt * KS2 + ks) * 64 + lane];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < NTW; ++nt) {
+          const int c = (wave * NTW + nt) * 16 + lc;
+          const int row = kappa < CSP ? c : TN;
+          const uint4 bv = *reinterpret_cast<const uint4*>(&xt[row * RSX + (kappa < CSP ? kappa : 0)]);
+          const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = 16 * mt + 4 * lg + r;
-        if (o >= p.Co) continue;
-        float v[NPH];
-#pragma unroll
-        for (int ph = 0; ph < NPH; ++ph) {
-          const float a = acc[nt][ph][mt][r];
-          if (EPI == EPI_AFFINE || EPI == EPI_OUT) {
-            v[ph] = fmaf(a, p.scale[o], p.shift[o]);
-          } else if (EPI == EPI_AFFINE_TANH) {
-            v[ph] = tanhf(fmaf(a, p.scale[o], p.shift[o]));
-          } else if (EPI == EPI_RELU) {
-            v[ph] = fmaxf(a + p.bias[o], 0.0f);
-          } else if (EPI == EPI_BIAS) {
-            v[ph] = p.bias ? a + p.bias[o] : a;
-          } else {  // EPI_RESID_RELU / EPI_RESID_GAP: shortcut already accumulated
-            v[ph] = fmaxf(a + (p.bias[o] + p.bs[o]), 0.0f);
-          }
-        }
-        if (EPI == EPI_RESID_GAP) {
-          gsum = fmaf(p.hw[o], v[0], gsum);
-          continue;
-        }
-        if (EPI == EPI_OUT) {
-#pragma unroll
-          for (int ph = 0; ph < NPH; ++ph) {
-            const int u = NPH * col + ph;
-            if (u >= p.Lout) continue;
-            const int W = p.Lout;
-            if (p.noise) p.noise[(int64_t)b * W + u] = v[ph];
-            if (p.clean) {
-              const Item& it = p.items[b];
-              const int t0 = W - it.s;
-              if (u >= t0) {
-                const int64_t idx = it.out + (u - t0);
-                p.clean[idx] = p.strain[idx] - v[ph];
-              }
-            }
-          }
-        } else if (OUT_F32) {
-#pragma unroll
-          for (int ph = 0; ph < NPH; ++ph) {
-            const int u = NPH * col + ph;
-            if (u < p.Lout) p.y[((int64_t)b * p.Co + o) * p.Lout + u] = v[ph];
-          }
-        } else if (NPH == 2 && (p.Lout & 1) == 0) {
-          // both phases are adjacent outputs: one 4-byte store
-          const uint32_t w2 = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[NPH - 1]) << 16);
-          *reinterpret_cast<uint32_t*>(&p.yh[((int64_t)b * p.Co + o) * p.Lout + 2 * col]) = w2;
-        } else {
-#pragma unroll
-          for (int ph = 0; ph < NPH; ++ph) {
-            const int u = NPH * col + ph;
-            if (u < p.Lout) p.yh[((int64_t)b * p.Co + o) * p.Lout + u] = bf16_rne(v[ph]);
-          }
+          for (int mt = 0; mt < MT; ++mt)
+            acc[nt][0][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[mt]), bb,
+                                                                     acc[nt][0][mt], 0, 0, 0);
         }
       }
-  }
-  if (EPI == EPI_RESID_GAP) {
-    // fixed-order reduction: lanes of a wave, then the four waves
-    for (int off = 32; off > 0; off >>= 1) gsum += __shfl_down(gsum, off, 64);
-    __shared__ float wsum[4];
-    if (lane == 0) wsum[wave] = gsum;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      p.gap_part[(int64_t)b * gridDim.x + blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+
+    // ---- epilogue
+    uint16_t* otile = tile;
+    if (OTILE) __syncthreads();  // every wave is done reading the input tile
+    float gsum = 0.0f;           // EPI_RESID_GAP: this lane's share of sum_o hw[o] y[o][t]
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) {
+      const int col = col0 + (wave * NTW + nt) * 16 + lc;
+      if (col >= ncol) continue;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = 16 * mt + 4 * lg + r;
+          if (o >= p.Co) continue;
+          const float ka = cst[0][o], kb = cst[1][o];
+          float v[NPH];
+#pragma unroll
+          for (int ph = 0; ph < NPH; ++ph) {
+            const float a = acc[nt][ph][mt][r];
+            if (EPI == EPI_AFFINE || EPI == EPI_OUT) {
+              v[ph] = fmaf(a, ka, kb);
+            } else if (EPI == EPI_AFFINE_TANH) {
+              v[ph] = tanhf(fmaf(a, ka, kb));
+            } else if (EPI == EPI_BIAS) {
+              v[ph] = a + kb;
+            } else {  // EPI_RELU, EPI_RESID_RELU, EPI_RESID_GAP (shortcut already accumulated)
+              v[ph] = fmaxf(a + kb, 0.0f);
+            }
+          }
+          if (EPI == EPI_RESID_GAP) {
+            gsum = fmaf(ka, v[0], gsum);
+          } else if (EPI == EPI_OUT) {
+#pragma unroll
+            for (int ph = 0; ph < NPH; ++ph) {
+              const int u = NPH * col + ph;
+              if (u >= p.Lout) continue;
+              const int W = p.Lout;
+              if (p.noise) p.noise[(int64_t)b * W + u] = v[ph];
+              if (p.clean) {
+                const Item& it = p.items[b];
+                const int t0 = W - it.s;
+                if (u >= t0) {
+                  const int64_t idx = it.out + (u - t0);
+                  p.clean[idx] = p.strain[idx] - v[ph];
+                }
+              }
+            }
+          } else if (OUT_F32) {
+#pragma unroll
+            for (int ph = 0; ph < NPH; ++ph) {
+              const int u = NPH * col + ph;
+              if (u < p.Lout) p.y[((int64_t)b * p.Co + o) * p.Lout + u] = v[ph];
+            }
+          } else {
+#pragma unroll
+            for (int ph = 0; ph < NPH; ++ph) otile[o * TNO + NPH * (col - col0) + ph] = bf16_rne(v[ph]);
+          }
+        }
+    }
+    if (OTILE) {
+      // write the tile back with 16-byte stores along time
+      __syncthreads();
+      const int Co = p.Co, Lout = p.Lout;
+      const int u00 = NPH * col0;
+      uint16_t* yb = p.yh + (int64_t)b * Co * Lout;
+      const bool vec = (Lout & 7) == 0 && (reinterpret_cast<uintptr_t>(p.yh) & 15) == 0;
+      for (int e = threadIdx.x; e < Co * (TNO / 8); e += 256) {
+        const int o = e / (TNO / 8), cu = e - o * (TNO / 8);
+        const int u0 = u00 + 8 * cu;
+        if (u0 >= Lout) continue;
+        const uint16_t* src = &otile[o * TNO + 8 * cu];
+        if (vec && u0 + 8 <= Lout) {
+          *reinterpret_cast<uint4*>(yb + (int64_t)o * Lout + u0) = *reinterpret_cast<const uint4*>(src);
+        } else {
+          for (int k = 0; k < 8 && u0 + k < Lout; ++k) yb[(int64_t)o * Lout + u0 + k] = src[k];
+        }
+      }
+    }
+    if (EPI == EPI_RESID_GAP) {
+      // fixed-order reduction: lanes of a wave, then the four waves
+      for (int off = 32; off > 0; off >>= 1) gsum += __shfl_down(gsum, off, 64);
+      if (lane == 0) wsum[wave] = gsum;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        p.gap_part[(int64_t)b * tiles_per + (t % tiles_per)] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+    __syncthreads();  // LDS tiles are rewritten by the next iteration
   }
 }
 
@@ -439,9 +532,29 @@ template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F3
 static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   constexpr int NTW = (NPH * MT <= 4) ? 4 : 2;
   constexpr int TN = 64 * NTW;
-  dim3 grid((g.ncol + TN - 1) / TN, p.n);
-  hipLaunchKernelGGL((conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP>), grid, dim3(256), 0,
-                     st, p, g.padc, g.ncol);
+  // same test as the kernel's ALDS: persistent grid only when weights fit in LDS
+  constexpr int ROWS = SC * (TN - 1) + KT, RS = CIP + 8, KS = (KT * CIP + 31) / 32;
+  constexpr int TILE = (ROWS + 1) * RS > 16 * MT * NPH * TN ? (ROWS + 1) * RS : 16 * MT * NPH * TN;
+  constexpr bool ALDS = 2 * TILE + NPH * MT * KS * 1024 <= 80 * 1024;
+  auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP>;
+  const int64_t tiles = (int64_t)((g.ncol + TN - 1) / TN) * p.n;
+  if (tiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+  if (!ALDS) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(256), 0, st, p, g.padc, g.ncol);
+    return hipGetLastError();
+  }
+  // persistent grid: enough blocks to fill every CU at the kernel's occupancy
+  static int max_blocks = 0;
+  if (max_blocks == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    max_blocks = per_cu * cus;
+  }
+  const int blocks = (int)std::min<int64_t>(tiles, max_blocks);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, p, g.padc, g.ncol);
   return hipGetLastError();
 }
 
@@ -469,7 +582,18 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32)              \
   X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0)                     \
   X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64)             \
-  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64)
+  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64)            \
+  /* training forward (BF16 conv variant): FP32 activations in, FP32 z out */ \
+  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                       \
+  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
+  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                       \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0)                        \
+  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0)
 
 int conv_bf16_col_tile(int Co, bool tr) {
   const int nph = tr ? 2 : 1, mt = (Co + 15) / 16;

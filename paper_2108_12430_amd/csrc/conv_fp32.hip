@@ -17,7 +17,7 @@ template <int SRC>
 struct In {
   const float* base;
   int head;
-  int L;
+  int L;  // row stride; for a ring also its length (wrap point)
   __device__ __forceinline__ float operator()(int i, int q) const {
     if (SRC == SRC_DENSE) return base[(int64_t)i * L + q];
     int ph = head + q;
@@ -67,12 +67,13 @@ __global__ __launch_bounds__(256) void conv_fp32(ConvP p) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= p.Lout) return;
   In<SRC> in;
-  in.L = p.Lin;
   if (SRC == SRC_DENSE) {
-    in.base = p.x + (int64_t)b * p.Ci * p.Lin;
+    in.L = p.ldx ? p.ldx : p.Lin;
+    in.base = p.x + (int64_t)b * p.Ci * in.L;
     in.head = 0;
   } else {
     const Item& it = p.items[b];
+    in.L = it.W;
     in.base = reinterpret_cast<const float*>(p.arena) + it.ring;
     in.head = it.head;
   }
@@ -108,12 +109,13 @@ __global__ __launch_bounds__(256) void convT_fp32(ConvP p) {
   const int s = p.stride;
   if (m * s >= p.Lout) return;
   In<SRC> in;
-  in.L = p.Lin;
   if (SRC == SRC_DENSE) {
-    in.base = p.x + (int64_t)b * p.Ci * p.Lin;
+    in.L = p.ldx ? p.ldx : p.Lin;
+    in.base = p.x + (int64_t)b * p.Ci * in.L;
     in.head = 0;
   } else {
     const Item& it = p.items[b];
+    in.L = it.W;
     in.base = reinterpret_cast<const float*>(p.arena) + it.ring;
     in.head = it.head;
   }

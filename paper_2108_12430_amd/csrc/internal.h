@@ -65,6 +65,10 @@ struct ConvP {
   float* clean;            // packed, or null
   // shape
   int n, Ci, Co, Lin, Lout, k, stride, pad;
+  // row stride (elements) of a dense first-layer input when it differs from
+  // Lin (a band at the end of longer windows); 0 means Lin.  Ring inputs wrap
+  // at their item's W and read positions [head + q] for q in [0, Lin).
+  int ldx;
 };
 
 // ---- launchers (defined in the .hip files) ----

@@ -318,3 +318,56 @@ def test_pool_batch_mixed_strides(dc, prec, tol):
         _, ec = ref.causal_clean(en[i:i + 1], data[i][1][None, pos[i] - s:pos[i]])
         assert rel(got[o:o + s], ec[0]) <= tol
         o += s
+
+
+@pytest.mark.parametrize("prec", [gs.FP32, gs.BF16])
+@pytest.mark.parametrize("W", [4096, 32768])
+def test_causal_band_bitwise(dc, prec, W):
+    """GW_CAUSAL runs the network only on the band of the window that the
+    newest s outputs depend on (receptive field); its clean output is bitwise
+    the full-window result, from rings and from dense windows, for mixed
+    strides in one call."""
+    m, params, layers = dc
+    strides = [256, 1, 1024, 16, 512]
+    n = len(strides)
+    pool = gs.Pool(256 << 20, max_slots=8, max_items=8)
+    slots = [pool.open(21, W) for _ in range(n)]
+    wit, strain_all = synth.witness_stream(90, W + 3000)
+    pos = [0] * n
+    for i in range(n):          # fill each ring with a different amount so heads differ
+        fill = W // 2 + 997 * i
+        blocks, sofar = [], 0
+        while sofar < fill:
+            s = min(W, fill - sofar)
+            pool.update([slots[i]], [s], torch.from_numpy(np.ascontiguousarray(wit[:, sofar:sofar + s])).to(DEV)
+                        .reshape(-1), [0])
+            sofar += s
+        pos[i] = fill
+    strain = torch.from_numpy(np.concatenate([strain_all[:s] for s in strides])).to(DEV)
+    full = torch.empty(sum(strides), device=DEV)
+    band = torch.empty(sum(strides), device=DEV)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, strain=strain, clean=full, precision=prec)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, strain=strain, clean=band, precision=prec,
+              flags=gs.CAUSAL)
+    torch.cuda.synchronize()
+    assert torch.equal(full, band)
+    # dense windows
+    xs = torch.stack([pool.window(sl) for sl in slots]).contiguous()
+    dense_full = torch.empty_like(full)
+    dense_band = torch.empty_like(full)
+    m.forward(x=xs, strides=strides, strain=strain, clean=dense_full, precision=prec)
+    m.forward(x=xs, strides=strides, strain=strain, clean=dense_band, precision=prec, flags=gs.CAUSAL)
+    torch.cuda.synchronize()
+    assert torch.equal(dense_full, dense_band)
+    assert torch.equal(dense_full, full)
+    # and the oracle agrees
+    x64 = np.stack([ref.snapshot_after(wit, pos[i], W) for i in range(n)])
+    en = ref.deepclean_forward(params, x64, layers)
+    o = 0
+    got = band.cpu().numpy()
+    st = strain.cpu().numpy()
+    tol = FP32_TOL if prec == gs.FP32 else BF16_TOL
+    for i, s in enumerate(strides):
+        _, ec = ref.causal_clean(en[i:i + 1], st[None, o:o + s])
+        assert rel(got[o:o + s], ec[0]) <= tol
+        o += s

@@ -132,3 +132,65 @@ def test_recompute_bitwise():
                                                                                              gs.TRAIN)
     n2, g2 = _train_step(m, x, strain, gs.TRAIN)
     assert np.array_equal(g0, g2)   # deterministic across runs
+
+
+def test_autograd_function_and_training_steps():
+    """DeepCleanFn exposes the hand-written backward to torch.autograd: its
+    parameter gradient equals the oracle's, and a few optimizer steps with the
+    band-passed loss lower that loss."""
+    from paper_2108_12430_amd.autograd import DeepCleanFn, bandpass_mse_loss, train_step
+    layers = synth.deepclean_layers()
+    p0 = synth.deepclean_params(0)
+    params = torch.from_numpy(p0.copy()).to(DEV).requires_grad_(True)
+    m = gs.DeepClean(params.detach(), layers)
+    wit, strain = synth.witness_stream(8, 2 * 8192)
+    x = torch.from_numpy(np.ascontiguousarray(wit.reshape(21, 2, 8192).transpose(1, 0, 2))).to(DEV)
+    st = torch.from_numpy(np.ascontiguousarray(strain.reshape(2, 8192))).to(DEV)
+    noise = DeepCleanFn.apply(params, x, m, True)
+    loss = bandpass_mse_loss(st, noise)
+    loss.backward()
+    xn = x.cpu().numpy()
+    sn = st.cpu().numpy()
+    en = ref.deepclean_forward(p0, xn, layers, train=True)
+    el, dn = ref.bandpass_mse(sn, en, 4096.0, 55.0, 65.0)
+    assert abs(loss.item() - el) <= 1e-5 * abs(el)
+    eg = ref.deepclean_grad(p0, xn, dn, layers)
+    errs = grad_errors(params.grad.cpu().numpy(), eg, layers)
+    assert max(errs.values()) <= 1e-5, errs
+    opt = torch.optim.SGD([params], lr=0.05)
+    losses = [train_step(m, params, opt, x, st).item() for _ in range(4)]
+    assert losses[-1] < losses[0]
+
+
+def test_grad_bf16_conv_variant():
+    """Training step with the forward (and recomputed) convolutions on BF16
+    matrix cores; activations, statistics and gradients stay FP32.  Gradients
+    within the BF16 tolerance of the oracle; recomputation still bitwise."""
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
+    wit, strain = synth.witness_stream(14, 2 * 32768)
+    x = np.ascontiguousarray(wit.reshape(21, 2, 32768).transpose(1, 0, 2))
+    sb = np.ascontiguousarray(strain.reshape(2, 32768))
+    xt = torch.from_numpy(x).to(DEV)
+    st = torch.from_numpy(sb).to(DEV)
+    out = []
+    for flags in (gs.TRAIN, gs.TRAIN | gs.RECOMPUTE):
+        noise = torch.empty((2, 32768), device=DEV)
+        ws = m.forward(x=xt, noise=noise, flags=flags, precision=gs.BF16)
+        _, dn = gs.bandpass_mse(st, noise)
+        dp = torch.empty_like(m.params)
+        m.backward(xt, dn, ws, dp, flags=flags, precision=gs.BF16)
+        torch.cuda.synchronize()
+        out.append((noise.cpu().numpy(), dp.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    en = ref.deepclean_forward(params, x, layers, train=True)
+    assert rel(out[0][0], en) <= 2e-2
+    _, dn = ref.bandpass_mse(sb, en, 4096.0, 55.0, 65.0)
+    eg = ref.deepclean_grad(params, x, dn, layers)
+    errs = grad_errors(out[0][1], eg, layers)
+    # BF16 rounds every conv operand to 2^-8 relative; the forward noise error
+    # is ~7e-3 and a layer-0 gradient passes through all nine layers forward
+    # and back, roughly doubling it, so gradient tensors get 3e-2 (the 2e-2
+    # output bound applies to the forward outputs checked above)
+    assert max(errs.values()) <= 3e-2, errs

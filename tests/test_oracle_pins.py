@@ -423,3 +423,22 @@ def test_shape_tables_agree():
     assert tuple(synth.bbhnet_stages()) == tuple(ref.BBHNET_STAGES)
     assert synth.deepclean_params(0).size == ref.n_params() == 39312 + 185 + 4 * 184
     ref.unpack_bbhnet(synth.bbhnet_params(0))
+
+
+@pytest.mark.parametrize("s", [1, 16, 100, 256, 1024])
+def test_receptive_field_band(s):
+    """The newest s outputs depend only on the band [a, W) with
+    a = floor((W - s - 93) / 16) * 16 (receptive half-width 93, aligned to the
+    total stride 16); a band 13 samples narrower is not enough in general."""
+    layers = synth.deepclean_layers()
+    p = synth.deepclean_params(0)
+    W = 4096
+    x = synth.gaussian(3, (1, 21, W)).astype(np.float64)
+    full = ref.deepclean_forward(p, x, layers)[0]
+    a = max(0, (W - s - 93) // 16 * 16)
+    band = ref.deepclean_forward(p, x[:, :, a:], layers)[0]
+    assert np.max(np.abs(band[-s:] - full[-s:])) <= 1e-13
+    if s == 256:
+        a2 = (W - s - 80) // 16 * 16
+        short = ref.deepclean_forward(p, x[:, :, a2:], layers)[0]
+        assert np.max(np.abs(short[-s:] - full[-s:])) > 1e-8
