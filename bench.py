@@ -77,6 +77,15 @@ def algorithmic(name, precision, layers, dc_s, bb_s):
         else:
             by += n * co * Lo * esz
         return 2.0 * macs, float(by)
+    if kind == "dc_fused_bf16":
+        # whole network per window: input read once from the BF16 ring
+        # shadow, strain read and clean written once; activations stay on chip
+        n = N_DC
+        macs = 0
+        for (typ, ci, co, k, Li, Lo) in layer_shapes(layers, DC_W):
+            macs += co * Lo * ci * k if typ == "conv" else ci * Li * co * k
+        by = n * DC_C * DC_W * 2 + 2 * 4 * int(dc_s.sum())
+        return 2.0 * macs * n, float(by)
     if kind.startswith("bbh_conv"):
         st = int(tag[1:])
         n, L = N_BB, BB_W

@@ -67,6 +67,8 @@ extern "C" {
                               save what deepclean_backward needs into ws      */
 #define GW_RECOMPUTE 2u    /* with GW_TRAIN: save only checkpoints, recompute
                               the rest in deepclean_backward                   */
+#define GW_LAYERWISE 8u    /* deepclean_forward BF16 inference: run one kernel per
+                              layer instead of the fused whole-network kernel  */
 #define GW_CAUSAL 4u       /* deepclean_forward inference: compute only what the
                               fully-online output needs (the newest s samples
                               depend on a band of about s + 93 input samples at
@@ -205,7 +207,10 @@ int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t pre
  * stride so every layer's sample grid coincides with the full window's).
  * Returns GW_EINVAL if ws_bytes is too small (the size deepclean_workspace
  * returns for the same n, W, precision and flags always suffices).
- * W must be a multiple of 16 (four stride-2 stages).
+ * W must be a multiple of 16 (four stride-2 stages).  For the reference
+ * network shape, GW_BF16 inference runs one fused kernel that keeps every
+ * intermediate activation on chip (unless GW_LAYERWISE is given); both
+ * variants agree within the BF16 tolerance and each is bitwise reproducible.
  */
 int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, const float* x,
                       int32_t n, int32_t W, const int32_t* strides, const float* strain, float* noise,

@@ -407,6 +407,7 @@ struct gw_model {
   char* packed = nullptr;
   Stager stager;
   bool bf16_all = false;
+  bool fused = false;  // reference DeepClean shape: whole-network BF16 kernel available
 };
 
 namespace {
@@ -469,6 +470,23 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
       m.bf16_all = m.bf16_all && ly.bf16;
     }
     m.c_in = m.layers[0].ci;
+    {
+      const int Ln = (int)m.layers.size();
+      std::vector<int> ci(Ln), co(Ln), ty(Ln), k(Ln), st(Ln), pd(Ln), op(Ln), bn(Ln);
+      for (int l = 0; l < Ln; ++l) {
+        const auto& ly = m.layers[l];
+        ci[l] = ly.ci;
+        co[l] = ly.co;
+        ty[l] = ly.type;
+        k[l] = ly.k;
+        st[l] = ly.s;
+        pd[l] = ly.p;
+        op[l] = ly.op;
+        bn[l] = ly.bn;
+      }
+      m.fused = m.bf16_all && gw::dc_fused_supported(ci.data(), co.data(), ty.data(), k.data(), st.data(),
+                                                     pd.data(), op.data(), bn.data(), Ln);
+    }
   } else if (kind == GW_MODEL_BBHNET) {
     const int Sn = desc[0];
     if (Sn < 1 || Sn > 8 || len != 2 + Sn) return fail(GW_EINVAL, "bad BBHnet description length");
@@ -807,7 +825,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
   if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
   if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
-  if (flags & ~(GW_TRAIN | GW_RECOMPUTE | GW_CAUSAL)) return fail(GW_EINVAL, "bad flags");
+  if (flags & ~(GW_TRAIN | GW_RECOMPUTE | GW_CAUSAL | GW_LAYERWISE)) return fail(GW_EINVAL, "bad flags");
   if ((flags & GW_CAUSAL) && (flags & GW_TRAIN)) return fail(GW_EINVAL, "GW_CAUSAL is for inference");
   if ((flags & GW_CAUSAL) && (!clean || noise))
     return fail(GW_EINVAL, "GW_CAUSAL computes only the clean output (noise must be NULL)");
@@ -830,7 +848,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   }
   const int Wb = W - a_band;
   DcWs w;
-  CHK(dc_ws_layout(m, n, Wb, precision, flags & ~GW_CAUSAL, w));
+  CHK(dc_ws_layout(m, n, Wb, precision, flags & ~(GW_CAUSAL | GW_LAYERWISE), w));
   if (ws_bytes < w.total)
     return fail(GW_EINVAL, "workspace too small: need " + std::to_string(w.total) + " bytes");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GW_EINVAL, "workspace not 256-byte aligned");
@@ -880,6 +898,28 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   char* wsb = reinterpret_cast<char*>(ws);
   const int L = (int)m->layers.size();
   const void* arena = pool ? pool->arena : nullptr;
+  if (!(flags & GW_TRAIN) && precision == GW_BF16 && m->fused && !(flags & GW_LAYERWISE)) {
+    // whole network in one kernel, activations on chip
+    gw::ConvP p{};
+    p.n = n;
+    p.items = dev_items;
+    p.arena = arena;
+    p.x = x ? x + a_band : nullptr;
+    p.ldx = x ? W : 0;
+    p.noise = noise;
+    p.clean = clean;
+    p.strain = strain;
+    const uint16_t* wpk[9];
+    const float* sc[9];
+    const float* sh[9];
+    for (int l = 0; l < 9; ++l) {
+      wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + m->layers[l].wbf);
+      sc[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].scale);
+      sh[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].shift);
+    }
+    LAUNCH("dc_fused_bf16", st, gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, st));
+    return GW_OK;
+  }
   if (!(flags & GW_TRAIN)) {
     const float* in = x ? x + a_band : nullptr;
     for (int l = 0; l < L; ++l) {

@@ -27,11 +27,13 @@ namespace gw {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// float -> bfloat16 bits, round to nearest even; NaNs stay (quiet) NaNs.
+// Written without a branch so it compiles to straight-line selects.
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t q = (u >> 16) | 0x40u;
+  return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? q : r);
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -143,10 +145,10 @@ hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k
 // its 8 positions with one 16-byte load (32 bytes for FP32 input) when the
 // chunk is aligned and inside the signal, element by element otherwise.
 // ---------------------------------------------------------------------------
-template <int CIP, int ROWS, int IN>
+template <int CIP, int ROWS, int IN, int NTHR = 256>
 struct InRaw {
-  static constexpr int NCHMAX = (ROWS + 7 + 7) / 8;          // 8-position chunks per channel
-  static constexpr int ITEMS = (NCHMAX * CIP + 255) / 256;    // (channel, chunk) items per thread
+  static constexpr int NCHMAX = (ROWS + 7 + 7) / 8;             // 8-position chunks per channel
+  static constexpr int ITEMS = (NCHMAX * CIP + NTHR - 1) / NTHR;  // (channel, chunk) items per thread
   static constexpr int NV = IN == IN_F32 ? 2 : 1;
   uint4 v[ITEMS][NV];  // raw 16-byte pieces (two for FP32 input)
   uint32_t f32mask;    // items whose v[it][0..1] still hold 8 FP32 values
@@ -157,9 +159,9 @@ struct InRaw {
 // (channel, 8-position chunk) with the channel varying fastest across lanes.
 // Each item is one 16-byte load (two for FP32 input) when the chunk is
 // aligned and inside the signal, element by element otherwise.
-template <int CIP, int ROWS, int IN>
-__device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN>& R, const ConvP& p, int b, int q0) {
-  constexpr int ITEMS = InRaw<CIP, ROWS, IN>::ITEMS;
+template <int CIP, int ROWS, int IN, int NTHR = 256>
+__device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN, NTHR>& R, const ConvP& p, int b, int q0) {
+  constexpr int ITEMS = InRaw<CIP, ROWS, IN, NTHR>::ITEMS;
   const int Ci = p.Ci, Lin = p.Lin;  // positions q in [0, Lin) exist; others are zero padding
   const int qa = q0 - (((q0 % 8) + 8) % 8);  // floor to a multiple of 8
   const int nch = (q0 + ROWS - qa + 7) / 8;
@@ -184,7 +186,7 @@ __device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN>& R, const ConvP&
   R.f32mask = 0;
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const int e = threadIdx.x + 256 * it;
+    const int e = threadIdx.x + NTHR * it;
     const int i = e % CIP, ch = e / CIP;
     const int qc = qa + 8 * ch;
     R.v[it][0] = make_uint4(0, 0, 0, 0);
@@ -231,14 +233,16 @@ __device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN>& R, const ConvP&
 
 // Write a loaded tile into LDS ([row][channel], row stride RS) plus the zero
 // row used by padded K entries.
-template <int CIP, int ROWS, int RS, int IN>
-__device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROWS, IN>& R, int q0) {
-  constexpr int ITEMS = InRaw<CIP, ROWS, IN>::ITEMS;
+// HALF > 0 stores row r at (r & 1) * HALF + (r >> 1): even rows first, then
+// odd rows, so a stride-2 reader walks consecutive LDS rows.
+template <int CIP, int ROWS, int RS, int IN, int NTHR = 256, int HALF = 0>
+__device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROWS, IN, NTHR>& R, int q0) {
+  constexpr int ITEMS = InRaw<CIP, ROWS, IN, NTHR>::ITEMS;
   const int qa = q0 - (((q0 % 8) + 8) % 8);
   const int nch = (q0 + ROWS - qa + 7) / 8;
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
-    const int e = threadIdx.x + 256 * it;
+    const int e = threadIdx.x + NTHR * it;
     const int i = e % CIP, ch = e / CIP;
     if (ch >= nch) continue;
     uint16_t v[8];
@@ -257,10 +261,12 @@ __device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROW
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int r = r0 + k;
-      if (r >= 0 && r < ROWS) tile[r * RS + i] = v[k];
+      const int pr = HALF ? (r & 1) * HALF + (r >> 1) : r;
+      if (r >= 0 && r < ROWS) tile[pr * RS + i] = v[k];
     }
   }
-  for (int e = threadIdx.x; e < RS; e += 256) tile[ROWS * RS + e] = 0;
+  constexpr int PZ = HALF ? (ROWS & 1) * HALF + (ROWS >> 1) : ROWS;
+  for (int e = threadIdx.x; e < RS; e += NTHR) tile[PZ * RS + e] = 0;
 }
 
 // Shortcut tile for the residual stage: row c holds the stage input at
@@ -641,6 +647,321 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
   GW_BF16_VARIANTS(GW_LAUNCH)
 #undef GW_LAUNCH
   return hipErrorNotSupported;
+}
+
+}  // namespace gw
+
+namespace gw {
+
+// ===========================================================================
+// Fused DeepClean forward (BF16).  One block computes T consecutive output
+// samples of one window through all nine layers; every intermediate
+// activation stays in LDS.  Working backwards from the output tile [u0, u0+T)
+// each layer's needed output positions are a fixed range around its scaled
+// tile start (see kFused below); the input tile is the window's samples
+// [u0 - 93, u0 + T + 93) (the receptive field).  Positions outside a layer's
+// signal are stored as zeros, i.e. they are the next layer's zero padding, so
+// every output equals the layer-by-layer result up to summation order.
+// Layers: four k7 s2 p3 convs (C0 -> C1 -> C2 -> C3 -> C4) with folded BN +
+// tanh, four k7 s2 p3 op1 transposed convs (C4 -> C5 -> C6 -> C7 -> C8) as
+// two 4-tap phases with folded BN + tanh, and the k7 s1 p3 output conv
+// C8 -> 1 whose epilogue writes the noise and the causal clean output.
+// ===========================================================================
+namespace fused {
+
+#ifndef GW_FUSED_T
+#define GW_FUSED_T 1024
+#endif
+constexpr int T = GW_FUSED_T;  // output samples per block (a multiple of 256)
+static_assert(T % 256 == 0, "tile must hold whole 16-column MFMA tiles at every layer");
+#ifndef GW_FUSED_WAVES
+#define GW_FUSED_WAVES 16
+#endif
+constexpr int NW = GW_FUSED_WAVES;  // waves per block
+constexpr int NTHR = 64 * NW;
+constexpr int C[10] = {21, 8, 16, 32, 64, 32, 16, 8, 8, 1};
+constexpr int cip(int c) { return (c + 7) / 8 * 8; }
+// LDS row stride (elements): an odd multiple of 8, so 16 lanes reading 16 B
+// from 16 consecutive rows hit 16 distinct 16 B bank groups
+constexpr int rs(int c) { return (cip(c) / 8) % 2 ? cip(c) : cip(c) + 8; }
+// row counts of the layer outputs a1..a8 (and x); row 0 of a_l sits at
+// (tile start scaled to layer l) + LO[l]
+constexpr int LO[10] = {-93, -45, -21, -9, -3, -3, -3, -3, -3, 0};
+constexpr int NR[10] = {T + 187, T / 2 + 91, T / 4 + 43, T / 8 + 19, T / 16 + 7,
+                        T / 8 + 7, T / 4 + 7, T / 2 + 7, T + 6, T};
+// output columns of layer l (convs: one per output row; transposed: one per
+// input-aligned position, producing rows 2c-1 and 2c)
+constexpr int NCOL[9] = {NR[1], NR[2], NR[3], NR[4], T / 16 + 4, T / 8 + 4, T / 4 + 4, T / 2 + 4, T};
+constexpr int NT(int l) { return (NCOL[l] + 15) / 16; }
+constexpr int SC(int l) { return l < 4 ? 2 : 1; }
+constexpr int KT(int l) { return l < 4 || l == 8 ? 7 : 4; }
+// rows of layer l's input buffer that its (padded) columns may read
+constexpr int rows_read(int l) { return SC(l) * (16 * NT(l) - 1) + KT(l); }
+constexpr int cap0(int l) { return (rows_read(l) > NR[l] ? rows_read(l) : NR[l]); }
+// inputs of the stride-2 layers are stored even rows first, then odd rows
+// (HALF rows each); the other inputs row by row
+constexpr int HALF(int l) { return l < 9 && SC(l) == 2 ? (cap0(l) + 1) / 2 : 0; }
+constexpr int cap(int l) { return HALF(l) ? 2 * HALF(l) : cap0(l); }  // rows of layer l's input buffer
+constexpr int mx(int a, int b) { return a > b ? a : b; }
+// ping-pong: inputs of layers 0,2,4,6,8 in buffer A, of layers 1,3,5,7 in B
+constexpr int BUFA = mx(mx(mx(cap(0) * rs(C[0]), cap(2) * rs(C[2])), mx(cap(4) * rs(C[4]), cap(6) * rs(C[6]))),
+                        cap(8) * rs(C[8]));
+constexpr int BUFB = mx(mx(cap(1) * rs(C[1]), cap(3) * rs(C[3])), mx(cap(5) * rs(C[5]), cap(7) * rs(C[7])));
+constexpr int MT(int l) { return (C[l + 1] + 15) / 16; }
+constexpr int NPH(int l) { return l >= 4 && l < 8 ? 2 : 1; }
+constexpr int KS(int l) { return (KT(l) * cip(C[l]) + 31) / 32; }
+constexpr int NFRAG(int l) { return NPH(l) * MT(l) * KS(l); }
+constexpr int WMAX = mx(mx(mx(NFRAG(0), NFRAG(1)), mx(NFRAG(2), NFRAG(3))),
+                        mx(mx(NFRAG(4), NFRAG(5)), mx(mx(NFRAG(6), NFRAG(7)), NFRAG(8))));
+
+}  // namespace fused
+
+struct FusedP {
+  const uint16_t* wpk[9];
+  const float* scale[9];
+  const float* shift[9];
+  int L[10];  // signal length of x and of each layer output (window W, W/2, ...)
+};
+
+// tanh for the BF16 path's epilogues: 1 - 2 / (exp(2x) + 1) on the hardware
+// exp2 and reciprocal (relative error far below the BF16 rounding of the
+// stored activations); saturates cleanly for large |x|.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * x, 64.0f));  // exp(2x)
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// One layer of the fused network: LDS in -> LDS out (or global for the last).
+template <int l>
+__device__ __forceinline__ void fused_layer(const uint16_t* in, uint16_t* out, const uint4* wl,
+                                            const float* ksc, const float* ksh, const uint16_t* zrow,
+                                            int pos0, int Lout, const ConvP* op, int b, int Wout) {
+  using namespace fused;
+  constexpr int CIN = cip(C[l]), RSI = rs(C[l]);
+  constexpr int CO = C[l + 1], CIPO = cip(C[l + 1]), RSO = rs(C[l + 1]);
+  constexpr int M = MT(l), P = NPH(l), K = KT(l), S = SC(l), KSn = KS(l), NTn = NT(l);
+  constexpr int NTC = NTn >= 4 * NW ? 4 : (NTn >= 2 * NW ? 2 : 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lc = lane & 15, lg = lane >> 4;
+  for (int nt0 = wave * NTC; nt0 < NTn; nt0 += NW * NTC) {
+    f32x4 acc[NTC][P][M];
+#pragma unroll
+    for (int a = 0; a < NTC; ++a)
+#pragma unroll
+      for (int ph = 0; ph < P; ++ph)
+#pragma unroll
+        for (int mt = 0; mt < M; ++mt) acc[a][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ks = 0; ks < KSn; ++ks) {
+      const int kappa = 32 * ks + 8 * lg;
+      const int jj = kappa / CIN, i0 = kappa - jj * CIN;
+      uint4 af[P][M];
+#pragma unroll
+      for (int ph = 0; ph < P; ++ph)
+#pragma unroll
+        for (int mt = 0; mt < M; ++mt) af[ph][mt] = wl[((ph * M + mt) * KSn + ks) * 64 + lane];
+#pragma unroll
+      for (int a = 0; a < NTC; ++a) {
+        if (nt0 + a >= NTn) break;  // wave-uniform
+        const int c = (nt0 + a) * 16 + lc;
+        constexpr int HI = HALF(l);
+        const int prow = HI ? (jj & 1) * HI + c + (jj >> 1) : S * c + jj;
+        const uint16_t* src = jj < K ? in + prow * RSI + i0 : zrow + i0;
+        const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src));
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph)
+#pragma unroll
+          for (int mt = 0; mt < M; ++mt)
+            acc[a][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[ph][mt]), bb,
+                                                                     acc[a][ph][mt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NTC; ++a) {
+      if (nt0 + a >= NTn) break;
+      const int c = (nt0 + a) * 16 + lc;
+      if (l == 8) {
+        // output conv (one channel: accumulator row 0, lanes 0..15): noise
+        // and the fully-online clean output
+        const int u = pos0 + c;
+        if (lg != 0 || c >= NR[9] || u < 0 || u >= Wout) continue;
+        const float v = fmaf(acc[a][0][0][0], ksc[0], ksh[0]);
+        if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
+        if (op->clean) {
+          const Item& it = op->items[b];
+          const int t0 = Wout - it.s;
+          if (u >= t0) {
+            const int64_t idx = it.out + (u - t0);
+            op->clean[idx] = op->strain[idx] - v;
+          }
+        }
+        continue;
+      }
+      // four consecutive channels per lane and row, packed into one 8 B store;
+      // channels >= CO and positions outside the signal are stored as zeros
+#pragma unroll
+      for (int mt = 0; mt < M; ++mt) {
+        const int o0 = 16 * mt + 4 * lg;
+        if (o0 >= CIPO) continue;
+        const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
+        const float4 sh4 = *reinterpret_cast<const float4*>(ksh + o0);
+        const float scv[4] = {sc4.x, sc4.y, sc4.z, sc4.w}, shv[4] = {sh4.x, sh4.y, sh4.z, sh4.w};
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph) {
+          const int row = P == 1 ? c : 2 * c + ph - 1;
+          if (row < 0 || row >= NR[l + 1]) continue;
+          const int u = pos0 + row;
+          const bool live = u >= 0 && u < Lout;
+          uint32_t h[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float t = fast_tanh(fmaf(acc[a][ph][mt][r], scv[r], shv[r]));
+            h[r] = bf16_rne(o0 + r < CO && live ? t : 0.0f);
+          }
+          constexpr int HO = HALF(l + 1);
+          const int prow = HO ? (row & 1) * HO + (row >> 1) : row;
+          *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        }
+      }
+    }
+  }
+}
+
+// Per-thread register copy of one layer's packed weights (at most WMAX
+// fragments of 64 x 16 B, two or four 16 B pieces per thread) and of its
+// per-channel scale/shift.  Named members, not an array, so the copy stays
+// in VGPRs across the layer computed meanwhile.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct WReg {
+  u32x4 w0, w1, w2, w3;
+  float sc, sh;
+};
+constexpr int WPIECES = fused::WMAX * 64 / fused::NTHR;  // 16 B pieces per thread
+static_assert(WPIECES * fused::NTHR == fused::WMAX * 64 && (WPIECES == 2 || WPIECES == 4), "weight staging split");
+
+__device__ __forceinline__ void fetch_w(WReg& r, const FusedP& f, int l, int nfrag, int co) {
+  const u32x4* src = reinterpret_cast<const u32x4*>(f.wpk[l]);
+  const int e = threadIdx.x, n = nfrag * 64;
+  if (e < n) r.w0 = src[e];
+  if (e + fused::NTHR < n) r.w1 = src[e + fused::NTHR];
+  if constexpr (WPIECES == 4) {
+    if (e + 2 * fused::NTHR < n) r.w2 = src[e + 2 * fused::NTHR];
+    if (e + 3 * fused::NTHR < n) r.w3 = src[e + 3 * fused::NTHR];
+  }
+  if (e < 64) {
+    const int oc = e < co ? e : co - 1;
+    r.sc = f.scale[l][oc];
+    r.sh = f.shift[l][oc];
+  }
+}
+
+__device__ __forceinline__ void put_w(const WReg& r, uint4* wlds, float* ksc, float* ksh, int nfrag) {
+  u32x4* wl = reinterpret_cast<u32x4*>(wlds);
+  const int e = threadIdx.x, n = nfrag * 64;
+  if (e < n) wl[e] = r.w0;
+  if (e + fused::NTHR < n) wl[e + fused::NTHR] = r.w1;
+  if constexpr (WPIECES == 4) {
+    if (e + 2 * fused::NTHR < n) wl[e + 2 * fused::NTHR] = r.w2;
+    if (e + 3 * fused::NTHR < n) wl[e + 3 * fused::NTHR] = r.w3;
+  }
+  if (e < 64) {
+    ksc[e] = r.sc;
+    ksh[e] = r.sh;
+  }
+}
+
+template <int IN>
+__global__ __launch_bounds__(fused::NTHR) void dc_fused(ConvP p, FusedP f) {
+  using namespace fused;
+  __shared__ __attribute__((aligned(16))) uint16_t bufA[BUFA];
+  __shared__ __attribute__((aligned(16))) uint16_t bufB[BUFB];
+  __shared__ __attribute__((aligned(16))) uint4 wl[WMAX * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t zrow[rs(64)];
+  __shared__ __attribute__((aligned(16))) float ksc[64];
+  __shared__ __attribute__((aligned(16))) float ksh[64];
+
+  const int W = f.L[0];
+  const int tiles = (W + T - 1) / T;
+  const int b = blockIdx.x / tiles;
+  const int u0 = (blockIdx.x % tiles) * T;
+  if (b >= p.n) return;
+
+  for (int e = threadIdx.x; e < rs(64); e += NTHR) zrow[e] = 0;
+  // a layer's weight fragments and constants are fetched into registers while
+  // the previous layer computes, then written to LDS between the layers
+  WReg wr;
+  fetch_w(wr, f, 0, NFRAG(0), C[1]);
+  {
+    // input tile rows [u0 - 93, u0 + T + 93) in [time][channel] layout
+    InRaw<cip(C[0]), NR[0], IN, NTHR> raw;
+    load_input<cip(C[0]), NR[0], IN, NTHR>(raw, p, b, u0 + LO[0]);
+    store_input<cip(C[0]), NR[0], rs(C[0]), IN, NTHR, HALF(0)>(bufA, raw, u0 + LO[0]);
+  }
+
+  // layer l reads the buffer holding a_l and writes a_{l+1}; u0 scaled per layer
+#define GW_FUSED_LAYER(l, IN_BUF, OUT_BUF, SCALE_DIV)                                                  \
+  __syncthreads();                                                                                     \
+  put_w(wr, wl, ksc, ksh, NFRAG(l));                                                                   \
+  __syncthreads();                                                                                     \
+  if (l < 8) fetch_w(wr, f, l < 8 ? l + 1 : l, NFRAG(l < 8 ? l + 1 : l), C[l < 8 ? l + 2 : l + 1]);    \
+  fused_layer<l>(IN_BUF, OUT_BUF, wl, ksc, ksh, zrow, u0 / (SCALE_DIV) + LO[l + 1], f.L[l + 1], &p, b, W);
+  GW_FUSED_LAYER(0, bufA, bufB, 2)
+  GW_FUSED_LAYER(1, bufB, bufA, 4)
+  GW_FUSED_LAYER(2, bufA, bufB, 8)
+  GW_FUSED_LAYER(3, bufB, bufA, 16)
+  GW_FUSED_LAYER(4, bufA, bufB, 8)
+  GW_FUSED_LAYER(5, bufB, bufA, 4)
+  GW_FUSED_LAYER(6, bufA, bufB, 2)
+  GW_FUSED_LAYER(7, bufB, bufA, 1)
+  GW_FUSED_LAYER(8, bufA, bufB, 1)
+#undef GW_FUSED_LAYER
+}
+
+bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,
+                        const int* pad, const int* op, const int* bn, int L) {
+  using namespace fused;
+  if (L != 9) return false;
+  for (int l = 0; l < 9; ++l) {
+    if (ci[l] != C[l] || co[l] != C[l + 1] || k[l] != 7 || pad[l] != 3) return false;
+    const bool tr = l >= 4 && l < 8;
+    if (type[l] != (tr ? 1 : 0) || s[l] != (l == 8 ? 1 : 2) || op[l] != (tr ? 1 : 0)) return false;
+    if (bn[l] != (l == 8 ? 0 : 1)) return false;
+  }
+  return true;
+}
+
+// p: n, items (ring input or clean outputs), arena, x (+ ldx), noise, clean,
+// strain; W = window (or band) length, a multiple of 16.
+hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
+                                const float* const* shift, int W, bool ring, hipStream_t st) {
+  using namespace fused;
+  if (W < 16 || W % 16) return hipErrorInvalidValue;
+  FusedP f;
+  for (int l = 0; l < 9; ++l) {
+    f.wpk[l] = wpk[l];
+    f.scale[l] = scale[l];
+    f.shift[l] = shift[l];
+  }
+  f.L[0] = W;
+  f.L[1] = W / 2;
+  f.L[2] = W / 4;
+  f.L[3] = W / 8;
+  f.L[4] = W / 16;
+  f.L[5] = W / 8;
+  f.L[6] = W / 4;
+  f.L[7] = W / 2;
+  f.L[8] = W;
+  f.L[9] = W;
+  ConvP q = p;
+  q.Lin = W;
+  q.Ci = C[0];
+  const int64_t blocks = (int64_t)p.n * ((W + T - 1) / T);
+  if (blocks > (int64_t)1 << 30) return hipErrorInvalidValue;
+  if (ring)
+    hipLaunchKernelGGL(dc_fused<IN_RING>, dim3((unsigned)blocks), dim3(NTHR), 0, st, q, f);
+  else
+    hipLaunchKernelGGL(dc_fused<IN_F32>, dim3((unsigned)blocks), dim3(NTHR), 0, st, q, f);
+  return hipGetLastError();
 }
 
 }  // namespace gw

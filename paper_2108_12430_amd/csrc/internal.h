@@ -76,6 +76,12 @@ hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, h
 hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool transposed);
 int conv_bf16_col_tile(int Co, bool transposed);  // output columns per block
+// Fused DeepClean network (21->8->16->32->64 convs, 64->32->16->8->8
+// transposed convs, 8->1 output conv, all k7 p3; BN+tanh on all but the last)
+bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,
+                        const int* pad, const int* op, const int* bn, int L);
+hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
+                                const float* const* shift, int W, bool ring, hipStream_t st);
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool transposed,
                             hipStream_t st);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgwstream.so")
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_ESTATE, GW_EHIP, GW_EUNSUPPORTED = range(6)
 FP32, BF16 = 0, 1
 MODEL_DEEPCLEAN, MODEL_BBHNET = 1, 2
-TRAIN, RECOMPUTE, CAUSAL = 1, 2, 4
+TRAIN, RECOMPUTE, CAUSAL, LAYERWISE = 1, 2, 4, 8
 _CODES = {1: "GW_EINVAL", 2: "GW_ENOMEM", 3: "GW_ESTATE", 4: "GW_EHIP", 5: "GW_EUNSUPPORTED"}
 
 EXPORTS = [

@@ -371,3 +371,25 @@ def test_causal_band_bitwise(dc, prec, W):
         _, ec = ref.causal_clean(en[i:i + 1], st[None, o:o + s])
         assert rel(got[o:o + s], ec[0]) <= tol
         o += s
+
+
+@pytest.mark.parametrize("W,n", [(32768, 2), (4096, 3), (16 * 67, 2), (16, 1)])
+def test_fused_vs_layerwise_bf16(dc, W, n):
+    """The whole-network fused BF16 kernel and the per-layer BF16 kernels both
+    match the oracle within the BF16 tolerance (full tiles, a ragged last tile,
+    the shortest window)."""
+    m, params, layers = dc
+    x = synth.gaussian(500 + W, (n, 21, W))
+    xt = torch.from_numpy(x).to(DEV)
+    a = torch.empty((n, W), device=DEV)
+    b = torch.empty((n, W), device=DEV)
+    m.forward(x=xt, noise=a, precision=gs.BF16)
+    m.forward(x=xt, noise=b, precision=gs.BF16, flags=gs.LAYERWISE)
+    torch.cuda.synchronize()
+    exp = ref.deepclean_forward(params, x, layers)
+    assert rel(a.cpu().numpy(), exp) <= BF16_TOL
+    assert rel(b.cpu().numpy(), exp) <= BF16_TOL
+    a2 = torch.empty_like(a)
+    m.forward(x=xt, noise=a2, precision=gs.BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a2)   # deterministic
