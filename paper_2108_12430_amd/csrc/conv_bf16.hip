@@ -670,7 +670,7 @@ namespace gw {
 namespace fused {
 
 #ifndef GW_FUSED_T
-#define GW_FUSED_T 1024
+#define GW_FUSED_T 768
 #endif
 constexpr int T = GW_FUSED_T;  // output samples per block (a multiple of 256)
 static_assert(T % 256 == 0, "tile must hold whole 16-column MFMA tiles at every layer");
@@ -711,8 +711,9 @@ constexpr int MT(int l) { return (C[l + 1] + 15) / 16; }
 constexpr int NPH(int l) { return l >= 4 && l < 8 ? 2 : 1; }
 constexpr int KS(int l) { return (KT(l) * cip(C[l]) + 31) / 32; }
 constexpr int NFRAG(int l) { return NPH(l) * MT(l) * KS(l); }
-constexpr int WMAX = mx(mx(mx(NFRAG(0), NFRAG(1)), mx(NFRAG(2), NFRAG(3))),
-                        mx(mx(NFRAG(4), NFRAG(5)), mx(mx(NFRAG(6), NFRAG(7)), NFRAG(8))));
+// all nine layers' weight fragments stay in LDS: layer l's start (in fragments)
+constexpr int WOFF(int l) { return l == 0 ? 0 : WOFF(l - 1) + NFRAG(l - 1); }
+constexpr int WTOT = WOFF(9);
 
 }  // namespace fused
 
@@ -723,198 +724,439 @@ struct FusedP {
   int L[10];  // signal length of x and of each layer output (window W, W/2, ...)
 };
 
-// tanh for the BF16 path's epilogues: 1 - 2 / (exp(2x) + 1) on the hardware
-// exp2 and reciprocal (relative error far below the BF16 rounding of the
-// stored activations); saturates cleanly for large |x|.
-__device__ __forceinline__ float fast_tanh(float x) {
-  const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * x, 64.0f));  // exp(2x)
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+// tanh for the fused epilogue from z = 2 x log2(e) (the factor is folded into
+// the BN scale and shift): 1 - 2 / (2^z + 1) on the hardware exp2 and
+// reciprocal.  2^z overflows to +inf for large z, giving exactly 1; relative
+// error is far below the BF16 rounding of the stored activations.
+__device__ __forceinline__ float tanh_scaled(float z) {
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f), 1.0f);
+}
+constexpr float kTwoLog2e = 2.8853900817779268f;
+
+namespace fused {
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+constexpr int mn(int a, int b) { return a < b ? a : b; }
+// 8-channel layers: the valid accumulator rows sit in lanes 0..31, so two
+// column tiles share one epilogue pass (lanes 32..63 take the second tile)
+constexpr bool COMPACT(int l) { return l < 8 && MT(l) == 1 && cip(C[l + 1]) == 8; }
+// column tiles per work unit: enough that every layer is one round of units
+constexpr int NTC(int l) { return COMPACT(l) ? mn(4, 2 * cdiv(NT(l), 2 * NW)) : mn(4, cdiv(NT(l), NW)); }
+constexpr int NG(int l) { return cdiv(NT(l), NTC(l)); }
+// per-layer table of B-fragment row offsets: KOFF[l][lg][ks] (elements) for
+// the 8 channels at kappa = 32 ks + 8 lg, i.e. tap jj = kappa / C_in and
+// channel i0 = kappa mod C_in; taps past the kernel (zero weights) read tap
+// K-1 instead, a row that holds finite values
+constexpr int KSMAX = 8;
+__host__ __device__ constexpr int koff(int l, int lg, int ks) {
+  const int kappa = 32 * ks + 8 * lg, jj = kappa / cip(C[l]), i0 = kappa - jj * cip(C[l]);
+  const int j = jj < KT(l) ? jj : KT(l) - 1;
+  return (HALF(l) ? (j & 1) * HALF(l) + (j >> 1) : j) * rs(C[l]) + i0;
+}
+// the (phase, channel tile) pairs of a layer with few column groups are
+// split over SPL waves
+constexpr int SPL(int l) {
+  return COMPACT(l) ? 1
+         : NPH(l) * MT(l) % 4 == 0 && NG(l) * 4 <= NW ? 4 : (NPH(l) * MT(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
+}
+}  // namespace fused
+
+// Two floats -> packed bf16 pair, first in the low half: the hardware
+// conversion, which rounds to nearest even exactly like bf16_rne (NaNs
+// included).
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
+}
+
+// BN + tanh of channels o0..o0+3 of one output row of layer l (scale and
+// shift pre-multiplied by 2 log2 e), stored as four bf16 in one 8 B LDS
+// write.  Positions outside the layer's signal are stored as zeros (the next
+// layer's padding); only tiles at a window edge (EDGE) have any.  Every
+// C_out here is a multiple of 8, so no stored channel is padding.
+template <int l, bool EDGE>
+__device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v, float4 sc, float4 sh, int pos0,
+                                        int Lout) {
+  using namespace fused;
+  constexpr int RSO = rs(C[l + 1]), HO = HALF(l + 1);
+  static_assert(C[l + 1] % 8 == 0, "stored channel groups are never padding");
+  if (row < 0 || row >= NR[l + 1]) return;
+  float t0 = tanh_scaled(fmaf(v[0], sc.x, sh.x)), t1 = tanh_scaled(fmaf(v[1], sc.y, sh.y));
+  float t2 = tanh_scaled(fmaf(v[2], sc.z, sh.z)), t3 = tanh_scaled(fmaf(v[3], sc.w, sh.w));
+  if (EDGE) {
+    const int u = pos0 + row;
+    const bool live = u >= 0 && u < Lout;
+    t0 = live ? t0 : 0.0f;
+    t1 = live ? t1 : 0.0f;
+    t2 = live ? t2 : 0.0f;
+    t3 = live ? t3 : 0.0f;
+  }
+  const int prow = HO ? (row & 1) * HO + (row >> 1) : row;
+  *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(pack_bf16x2(t0, t1), pack_bf16x2(t2, t3));
+}
+
+// Epilogue of one work unit (see fused_layer).
+template <int l, bool EDGE, int NTCl, int Q>
+__device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, int sp, int lc, int lg, uint16_t* out,
+                                          const float* ksc, const float* ksh, int pos0, int Lout, const ConvP* op,
+                                          int b, int Wout) {
+  using namespace fused;
+  constexpr int CIPO = cip(C[l + 1]), M = MT(l), P = NPH(l), NTn = NT(l), SP = SPL(l);
+  if constexpr (l == 8) {
+    // output conv (one channel: accumulator row 0, lanes 0..15): noise and
+    // the fully-online clean output
+#pragma unroll
+    for (int a = 0; a < NTCl; ++a) {
+      if (nt0 + a >= NTn) break;
+      const int c = (nt0 + a) * 16 + lc;
+      const int u = pos0 + c;
+      if (lg != 0 || c >= NR[9] || u < 0 || u >= Wout) continue;
+      const float v = fmaf(acc[a][0][0], ksc[0], ksh[0]);
+      if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
+      if (op->clean) {
+        const Item& it = op->items[b];
+        const int t0 = Wout - it.s;
+        if (u >= t0) {
+          const int64_t idx = it.out + (u - t0);
+          op->clean[idx] = op->strain[idx] - v;
+        }
+      }
+    }
+  } else if constexpr (COMPACT(l)) {
+    // tiles a, a+1: lanes 0..31 keep tile a's channels 0..7, lanes 32..63
+    // receive tile a+1's (its lanes 0..31) through a 32-lane swap
+    static_assert(SP == 1 && Q == P, "compact layers keep both phases in one unit");
+    const int o0 = 4 * (lg & 1);
+    const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
+    const float4 sh4 = *reinterpret_cast<const float4*>(ksh + o0);
+#pragma unroll
+    for (int a = 0; a < NTCl; a += 2) {
+      if (nt0 + a >= NTn) break;
+      if (a + 1 < NTCl && nt0 + a + 1 < NTn) {
+        const int c = (nt0 + a + (lg >> 1)) * 16 + lc;
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph) {
+          f32x4 v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            v[r] = __uint_as_float(__builtin_amdgcn_permlane32_swap(__float_as_uint(acc[a][ph][r]),
+                                                                    __float_as_uint(acc[a + 1][ph][r]), false,
+                                                                    false)[0]);
+          epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, v, sc4, sh4, pos0, Lout);
+        }
+      } else if (lg < 2) {
+        const int c = (nt0 + a) * 16 + lc;
+#pragma unroll
+        for (int ph = 0; ph < P; ++ph)
+          epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][ph], sc4, sh4, pos0, Lout);
+      }
+    }
+  } else {
+    // four consecutive channels per lane and row, one 8 B store each
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int q = sp + k * SP, ph = q / M, mt = q % M;
+      const int o0 = 16 * mt + 4 * lg;
+      if (o0 >= CIPO) continue;
+      const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
+      const float4 sh4 = *reinterpret_cast<const float4*>(ksh + o0);
+#pragma unroll
+      for (int a = 0; a < NTCl; ++a) {
+        if (nt0 + a >= NTn) break;
+        const int c = (nt0 + a) * 16 + lc;
+        epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][k], sc4, sh4, pos0, Lout);
+      }
+    }
+  }
 }
 
 // One layer of the fused network: LDS in -> LDS out (or global for the last).
+// Work units are (group of NTC column tiles, share of the (phase, channel
+// tile) pairs); unit u goes to wave u mod NW.  kt holds the layer's row of
+// the B-offset table.
 template <int l>
-__device__ __forceinline__ void fused_layer(const uint16_t* in, uint16_t* out, const uint4* wl,
-                                            const float* ksc, const float* ksh, const uint16_t* zrow,
-                                            int pos0, int Lout, const ConvP* op, int b, int Wout) {
+__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wl,
+                                            const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
+                                            const ConvP* op, int b, int Wout) {
   using namespace fused;
-  constexpr int CIN = cip(C[l]), RSI = rs(C[l]);
-  constexpr int CO = C[l + 1], CIPO = cip(C[l + 1]), RSO = rs(C[l + 1]);
-  constexpr int M = MT(l), P = NPH(l), K = KT(l), S = SC(l), KSn = KS(l), NTn = NT(l);
-  constexpr int NTC = NTn >= 4 * NW ? 4 : (NTn >= 2 * NW ? 2 : 1);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int RSI = rs(C[l]);
+  constexpr int KSn = KS(l), NTn = NT(l);
+  constexpr int NTCl = NTC(l), SP = SPL(l), Q = NPH(l) * MT(l) / SP;
+  constexpr int SX = HALF(l) ? 1 : SC(l);  // LDS rows between adjacent columns
+  static_assert(KSn <= KSMAX, "offset table width");
+  const int lane = tid & 63, wave = tid >> 6;
   const int lc = lane & 15, lg = lane >> 4;
-  for (int nt0 = wave * NTC; nt0 < NTn; nt0 += NW * NTC) {
-    f32x4 acc[NTC][P][M];
+  // this lane's B row offsets for the layer's K steps
+  int ko[KSMAX];
+  {
+    const int4 k0 = *reinterpret_cast<const int4*>(kt + KSMAX * lg);
+    const int4 k1 = *reinterpret_cast<const int4*>(kt + KSMAX * lg + 4);
+    ko[0] = k0.x; ko[1] = k0.y; ko[2] = k0.z; ko[3] = k0.w;
+    ko[4] = k1.x; ko[5] = k1.y; ko[6] = k1.z; ko[7] = k1.w;
+  }
+  // window-edge tiles store zeros outside the signal
+  const bool edge = pos0 < 0 || pos0 + NR[l + 1] > Lout;
+  for (int unit = wave; unit < NG(l) * SP; unit += NW) {
+    const int nt0 = (unit / SP) * NTCl, sp = unit % SP;  // wave-uniform
+    const uint16_t* colbase = in + ((nt0 * 16 + lc) * SX) * RSI;
+    const uint4* wq = wl + sp * KSn * 64 + lane;
+    f32x4 acc[NTCl][Q];
 #pragma unroll
-    for (int a = 0; a < NTC; ++a)
+    for (int a = 0; a < NTCl; ++a)
 #pragma unroll
-      for (int ph = 0; ph < P; ++ph)
+      for (int k = 0; k < Q; ++k) acc[a][k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int mt = 0; mt < M; ++mt) acc[a][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
     for (int ks = 0; ks < KSn; ++ks) {
-      const int kappa = 32 * ks + 8 * lg;
-      const int jj = kappa / CIN, i0 = kappa - jj * CIN;
-      uint4 af[P][M];
+      uint4 af[Q];
 #pragma unroll
-      for (int ph = 0; ph < P; ++ph)
+      for (int k = 0; k < Q; ++k) af[k] = wq[(k * SP * KSn + ks) * 64];  // pair q = sp + k SP = ph * M + mt
+      const uint16_t* src = colbase + ko[ks];
 #pragma unroll
-        for (int mt = 0; mt < M; ++mt) af[ph][mt] = wl[((ph * M + mt) * KSn + ks) * 64 + lane];
-#pragma unroll
-      for (int a = 0; a < NTC; ++a) {
+      for (int a = 0; a < NTCl; ++a) {
         if (nt0 + a >= NTn) break;  // wave-uniform
-        const int c = (nt0 + a) * 16 + lc;
-        constexpr int HI = HALF(l);
-        const int prow = HI ? (jj & 1) * HI + c + (jj >> 1) : S * c + jj;
-        const uint16_t* src = jj < K ? in + prow * RSI + i0 : zrow + i0;
-        const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src));
+        const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + a * 16 * SX * RSI));
 #pragma unroll
-        for (int ph = 0; ph < P; ++ph)
-#pragma unroll
-          for (int mt = 0; mt < M; ++mt)
-            acc[a][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[ph][mt]), bb,
-                                                                     acc[a][ph][mt], 0, 0, 0);
+        for (int k = 0; k < Q; ++k)
+          acc[a][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[k]), bb, acc[a][k], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int a = 0; a < NTC; ++a) {
-      if (nt0 + a >= NTn) break;
-      const int c = (nt0 + a) * 16 + lc;
-      if (l == 8) {
-        // output conv (one channel: accumulator row 0, lanes 0..15): noise
-        // and the fully-online clean output
-        const int u = pos0 + c;
-        if (lg != 0 || c >= NR[9] || u < 0 || u >= Wout) continue;
-        const float v = fmaf(acc[a][0][0][0], ksc[0], ksh[0]);
-        if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
-        if (op->clean) {
-          const Item& it = op->items[b];
-          const int t0 = Wout - it.s;
-          if (u >= t0) {
-            const int64_t idx = it.out + (u - t0);
-            op->clean[idx] = op->strain[idx] - v;
-          }
-        }
-        continue;
-      }
-      // four consecutive channels per lane and row, packed into one 8 B store;
-      // channels >= CO and positions outside the signal are stored as zeros
-#pragma unroll
-      for (int mt = 0; mt < M; ++mt) {
-        const int o0 = 16 * mt + 4 * lg;
-        if (o0 >= CIPO) continue;
-        const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
-        const float4 sh4 = *reinterpret_cast<const float4*>(ksh + o0);
-        const float scv[4] = {sc4.x, sc4.y, sc4.z, sc4.w}, shv[4] = {sh4.x, sh4.y, sh4.z, sh4.w};
-#pragma unroll
-        for (int ph = 0; ph < P; ++ph) {
-          const int row = P == 1 ? c : 2 * c + ph - 1;
-          if (row < 0 || row >= NR[l + 1]) continue;
-          const int u = pos0 + row;
-          const bool live = u >= 0 && u < Lout;
-          uint32_t h[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float t = fast_tanh(fmaf(acc[a][ph][mt][r], scv[r], shv[r]));
-            h[r] = bf16_rne(o0 + r < CO && live ? t : 0.0f);
-          }
-          constexpr int HO = HALF(l + 1);
-          const int prow = HO ? (row & 1) * HO + (row >> 1) : row;
-          *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-        }
-      }
-    }
+    if (edge)
+      fused_epi<l, true, NTCl, Q>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
+    else
+      fused_epi<l, false, NTCl, Q>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
   }
 }
 
-// Per-thread register copy of one layer's packed weights (at most WMAX
-// fragments of 64 x 16 B, two or four 16 B pieces per thread) and of its
-// per-channel scale/shift.  Named members, not an array, so the copy stays
-// in VGPRs across the layer computed meanwhile.
+// ---------------------------------------------------------------------------
+// Input staging of the fused kernel.  An item is (group of four channels,
+// 8-sample chunk): four 16 B loads (one per channel, BF16 ring shadow; two
+// per channel for FP32 input) that share one address computation, transposed
+// in registers into eight rows of four channels, each written with one 8 B
+// LDS store.  Lanes take consecutive channel groups first, so a row's groups
+// are contiguous in LDS.  Rows are stored even rows first, then odd rows
+// (layer 0 reads with stride 2).
+// ---------------------------------------------------------------------------
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-struct WReg {
-  u32x4 w0, w1, w2, w3;
-  float sc, sh;
-};
-constexpr int WPIECES = fused::WMAX * 64 / fused::NTHR;  // 16 B pieces per thread
-static_assert(WPIECES * fused::NTHR == fused::WMAX * 64 && (WPIECES == 2 || WPIECES == 4), "weight staging split");
-
-__device__ __forceinline__ void fetch_w(WReg& r, const FusedP& f, int l, int nfrag, int co) {
-  const u32x4* src = reinterpret_cast<const u32x4*>(f.wpk[l]);
-  const int e = threadIdx.x, n = nfrag * 64;
-  if (e < n) r.w0 = src[e];
-  if (e + fused::NTHR < n) r.w1 = src[e + fused::NTHR];
-  if constexpr (WPIECES == 4) {
-    if (e + 2 * fused::NTHR < n) r.w2 = src[e + 2 * fused::NTHR];
-    if (e + 3 * fused::NTHR < n) r.w3 = src[e + 3 * fused::NTHR];
-  }
-  if (e < 64) {
-    const int oc = e < co ? e : co - 1;
-    r.sc = f.scale[l][oc];
-    r.sh = f.shift[l][oc];
-  }
-}
-
-__device__ __forceinline__ void put_w(const WReg& r, uint4* wlds, float* ksc, float* ksh, int nfrag) {
-  u32x4* wl = reinterpret_cast<u32x4*>(wlds);
-  const int e = threadIdx.x, n = nfrag * 64;
-  if (e < n) wl[e] = r.w0;
-  if (e + fused::NTHR < n) wl[e + fused::NTHR] = r.w1;
-  if constexpr (WPIECES == 4) {
-    if (e + 2 * fused::NTHR < n) wl[e + 2 * fused::NTHR] = r.w2;
-    if (e + 3 * fused::NTHR < n) wl[e + 3 * fused::NTHR] = r.w3;
-  }
-  if (e < 64) {
-    ksc[e] = r.sc;
-    ksh[e] = r.sh;
-  }
-}
+namespace fused {
+constexpr int XG = cip(C[0]) / 4;                  // channel groups of x
+constexpr int XCH = (NR[0] + 7 + 7) / 8;           // chunks covering NR[0] rows at any alignment
+constexpr int XITEMS = cdiv(XG * XCH, NTHR);       // items per thread
+}  // namespace fused
 
 template <int IN>
-__global__ __launch_bounds__(fused::NTHR) void dc_fused(ConvP p, FusedP f) {
+struct XRaw {
+  static constexpr int NV = IN == IN_F32 ? 2 : 1;  // 16 B pieces per channel chunk
+  u32x4 v[fused::XITEMS][4][NV];
+};
+
+// one channel's 8-sample chunk at positions [qc, qc + 8) of the window; zeros
+// outside [0, Lin) and for channels >= Ci
+template <int IN>
+__device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint16_t* hrow, const float* frow,
+                                           int head, int ld, int Lin, int qc, bool vec) {
+  constexpr int NV = XRaw<IN>::NV;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) d[k] = u32x4{0u, 0u, 0u, 0u};
+  if (vec && qc >= 0 && qc + 8 <= Lin) {
+    if (IN == IN_F32) {
+      d[0] = *reinterpret_cast<const u32x4*>(frow + qc);
+      d[NV - 1] = *reinterpret_cast<const u32x4*>(frow + qc + 4);
+    } else {
+      int ph = qc;
+      if (IN == IN_RING) {
+        ph = head + qc;
+        if (ph >= ld) ph -= ld;
+      }
+      d[0] = *reinterpret_cast<const u32x4*>(hrow + ph);
+    }
+  } else {
+    uint32_t w[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int q = qc + e;
+      w[e] = 0;
+      if (q >= 0 && q < Lin) {
+        if (IN == IN_F32) {
+          w[e] = __float_as_uint(frow[q]);
+        } else {
+          int ph = q;
+          if (IN == IN_RING) {
+            ph = head + q;
+            if (ph >= ld) ph -= ld;
+          }
+          w[e] = hrow[ph];
+        }
+      }
+    }
+    if (IN == IN_F32) {
+      d[0] = u32x4{w[0], w[1], w[2], w[3]};
+      d[NV - 1] = u32x4{w[4], w[5], w[6], w[7]};
+    } else {
+      d[0] = u32x4{w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16), w[6] | (w[7] << 16)};
+    }
+  }
+}
+
+// Issue the loads of a tile's input rows [q0, q0 + NR[0]) of window b.
+template <int IN>
+__device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q0) {
+  using namespace fused;
+  const int Ci = p.Ci, Lin = p.Lin;
+  const int qa = q0 - (((q0 % 8) + 8) % 8);
+  const int nch = (q0 + NR[0] - qa + 7) / 8;
+  int head = 0, ld = p.ldx ? p.ldx : Lin;
+  const uint16_t* hbase = nullptr;
+  const float* fbase = nullptr;
+  bool vec;
+  if (IN == IN_RING) {
+    const Item& it = p.items[b];
+    head = it.head;
+    ld = it.W;
+    hbase = reinterpret_cast<const uint16_t*>(p.arena) + it.shadow;
+    vec = (ld & 7) == 0 && (head & 7) == 0 && (it.shadow & 7) == 0;
+  } else {
+    fbase = p.x + (int64_t)b * Ci * ld;
+    vec = (ld & 7) == 0 && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
+  }
+#pragma unroll
+  for (int it = 0; it < XITEMS; ++it) {
+    const int e = threadIdx.x + NTHR * it;
+    const int g = e % XG, ch = e / XG;
+    const int qc = qa + 8 * ch;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = 4 * g + k;
+      const bool on = ch < nch && i < Ci;
+      const int64_t ro = (int64_t)(on ? i : 0) * ld;
+      load_chunk<IN>(R.v[it][k], hbase + (IN == IN_RING ? ro : 0), fbase + (IN == IN_F32 ? ro : 0), head, ld,
+                     on ? Lin : 0, qc, vec);
+    }
+  }
+}
+
+// Write the staged rows to LDS (row stride RS, even/odd split at HALF).
+template <int IN>
+__device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q0) {
+  using namespace fused;
+  constexpr int RS = rs(C[0]), H = HALF(0), ROWS = NR[0];
+  static_assert(H > 0, "layer 0 reads its input with stride 2");
+  const int qa = q0 - (((q0 % 8) + 8) % 8);
+  const int nch = (q0 + ROWS - qa + 7) / 8;
+#pragma unroll
+  for (int it = 0; it < XITEMS; ++it) {
+    const int e = threadIdx.x + NTHR * it;
+    const int g = e % XG, ch = e / XG;
+    if (ch >= nch) continue;
+    // bf16 pairs of each channel: c[k][d] holds samples 2d, 2d+1
+    uint32_t c[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (IN == IN_F32) {
+        const u32x4 a = R.v[it][k][0], z = R.v[it][k][XRaw<IN>::NV - 1];
+        c[k][0] = pack_bf16x2(__uint_as_float(a.x), __uint_as_float(a.y));
+        c[k][1] = pack_bf16x2(__uint_as_float(a.z), __uint_as_float(a.w));
+        c[k][2] = pack_bf16x2(__uint_as_float(z.x), __uint_as_float(z.y));
+        c[k][3] = pack_bf16x2(__uint_as_float(z.z), __uint_as_float(z.w));
+      } else {
+        const u32x4 a = R.v[it][k][0];
+        c[k][0] = a.x; c[k][1] = a.y; c[k][2] = a.z; c[k][3] = a.w;
+      }
+    }
+    const int r0 = qa + 8 * ch - q0;  // row of the chunk's first sample
+    const bool full = r0 >= 0 && r0 + 8 <= ROWS;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int d = t >> 1;
+      uint32_t lo, hi;
+      if (t & 1) {
+        lo = (c[0][d] >> 16) | (c[1][d] & 0xffff0000u);
+        hi = (c[2][d] >> 16) | (c[3][d] & 0xffff0000u);
+      } else {
+        lo = (c[0][d] & 0xffffu) | (c[1][d] << 16);
+        hi = (c[2][d] & 0xffffu) | (c[3][d] << 16);
+      }
+      const int r = r0 + t;
+      if (full || (r >= 0 && r < ROWS))
+        *reinterpret_cast<uint2*>(tile + ((r & 1) * H + (r >> 1)) * RS + 4 * g) = make_uint2(lo, hi);
+    }
+  }
+}
+
+#ifndef GW_FUSED_WAVES_PER_SIMD
+#define GW_FUSED_WAVES_PER_SIMD 1
+#endif
+template <int IN>
+__global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused(ConvP p, FusedP f, int ntile) {
   using namespace fused;
   __shared__ __attribute__((aligned(16))) uint16_t bufA[BUFA];
   __shared__ __attribute__((aligned(16))) uint16_t bufB[BUFB];
-  __shared__ __attribute__((aligned(16))) uint4 wl[WMAX * 64];
-  __shared__ __attribute__((aligned(16))) uint16_t zrow[rs(64)];
-  __shared__ __attribute__((aligned(16))) float ksc[64];
-  __shared__ __attribute__((aligned(16))) float ksh[64];
+  __shared__ __attribute__((aligned(16))) uint4 wl[WTOT * 64];
+  __shared__ __attribute__((aligned(16))) int ktab[9][4][KSMAX];
+  __shared__ __attribute__((aligned(16))) float ksc[9][64];
+  __shared__ __attribute__((aligned(16))) float ksh[9][64];
 
   const int W = f.L[0];
-  const int tiles = (W + T - 1) / T;
-  const int b = blockIdx.x / tiles;
-  const int u0 = (blockIdx.x % tiles) * T;
-  if (b >= p.n) return;
+  const int tpw = (W + T - 1) / T;  // tiles per window
+  const int G = gridDim.x, j = blockIdx.x;
+  const int t0 = (int)((int64_t)ntile * j / G), t1 = (int)((int64_t)ntile * (j + 1) / G);
+  if (t0 >= t1) return;  // block-uniform
 
-  for (int e = threadIdx.x; e < rs(64); e += NTHR) zrow[e] = 0;
-  // a layer's weight fragments and constants are fetched into registers while
-  // the previous layer computes, then written to LDS between the layers
-  WReg wr;
-  fetch_w(wr, f, 0, NFRAG(0), C[1]);
-  {
-    // input tile rows [u0 - 93, u0 + T + 93) in [time][channel] layout
-    InRaw<cip(C[0]), NR[0], IN, NTHR> raw;
-    load_input<cip(C[0]), NR[0], IN, NTHR>(raw, p, b, u0 + LO[0]);
-    store_input<cip(C[0]), NR[0], rs(C[0]), IN, NTHR, HALF(0)>(bufA, raw, u0 + LO[0]);
+  XRaw<IN> raw;
+  load_x<IN>(raw, p, t0 / tpw, (t0 % tpw) * T + LO[0]);
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const uint4* src = reinterpret_cast<const uint4*>(f.wpk[l]);
+    for (int e = threadIdx.x; e < NFRAG(l) * 64; e += NTHR) wl[WOFF(l) * 64 + e] = src[e];
+    if (threadIdx.x < 64) {
+      const int oc = (int)threadIdx.x < C[l + 1] ? (int)threadIdx.x : C[l + 1] - 1;
+      const float g = l < 8 ? kTwoLog2e : 1.0f;  // tanh layers take z = 2 x log2(e)
+      ksc[l][threadIdx.x] = f.scale[l][oc] * g;
+      ksh[l][threadIdx.x] = f.shift[l][oc] * g;
+    }
+    if (threadIdx.x < 4 * KSMAX) {
+      const int lg = threadIdx.x / KSMAX, ks = threadIdx.x % KSMAX;
+      ktab[l][lg][ks] = ks < KS(l) ? koff(l, lg, ks) : 0;
+    }
   }
+  // input tile rows [u0 - 93, u0 + T + 93) in [time][channel] layout
+  store_x<IN>(bufA, raw, (t0 % tpw) * T + LO[0]);
+  __syncthreads();
 
-  // layer l reads the buffer holding a_l and writes a_{l+1}; u0 scaled per layer
-#define GW_FUSED_LAYER(l, IN_BUF, OUT_BUF, SCALE_DIV)                                                  \
-  __syncthreads();                                                                                     \
-  put_w(wr, wl, ksc, ksh, NFRAG(l));                                                                   \
-  __syncthreads();                                                                                     \
-  if (l < 8) fetch_w(wr, f, l < 8 ? l + 1 : l, NFRAG(l < 8 ? l + 1 : l), C[l < 8 ? l + 2 : l + 1]);    \
-  fused_layer<l>(IN_BUF, OUT_BUF, wl, ksc, ksh, zrow, u0 / (SCALE_DIV) + LO[l + 1], f.L[l + 1], &p, b, W);
-  GW_FUSED_LAYER(0, bufA, bufB, 2)
-  GW_FUSED_LAYER(1, bufB, bufA, 4)
-  GW_FUSED_LAYER(2, bufA, bufB, 8)
-  GW_FUSED_LAYER(3, bufB, bufA, 16)
-  GW_FUSED_LAYER(4, bufA, bufB, 8)
-  GW_FUSED_LAYER(5, bufB, bufA, 4)
-  GW_FUSED_LAYER(6, bufA, bufB, 2)
-  GW_FUSED_LAYER(7, bufB, bufA, 1)
-  GW_FUSED_LAYER(8, bufA, bufB, 1)
+  for (int t = t0; t < t1; ++t) {
+    const int b = t / tpw, u0 = (t % tpw) * T;
+    const bool more = t + 1 < t1;  // block-uniform
+    const int nb = (t + 1) / tpw, nq = ((t + 1) % tpw) * T + LO[0];
+    // FP32 input takes twice the registers: it is loaded after the last layer
+    constexpr bool PREFETCH = IN != IN_F32;
+    if (PREFETCH && more) load_x<IN>(raw, p, nb, nq);
+
+    // layer l reads the buffer holding a_l and writes a_{l+1}; u0 scaled per
+    // layer; an opaque copy of the thread index keeps each layer's address
+    // arithmetic inside the tile loop instead of live across it
+#define GW_FUSED_LAYER(l, IN_BUF, OUT_BUF, SCALE_DIV)                                                       \
+    {                                                                                                       \
+      int tid = threadIdx.x;                                                                                \
+      asm volatile("" : "+v"(tid));                                                                         \
+      fused_layer<l>(tid, IN_BUF, OUT_BUF, wl + WOFF(l) * 64, &ktab[l][0][0], ksc[l], ksh[l],              \
+                     u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);                              \
+      __syncthreads();                                                                                      \
+    }
+    GW_FUSED_LAYER(0, bufA, bufB, 2)
+    GW_FUSED_LAYER(1, bufB, bufA, 4)
+    GW_FUSED_LAYER(2, bufA, bufB, 8)
+    GW_FUSED_LAYER(3, bufB, bufA, 16)
+    GW_FUSED_LAYER(4, bufA, bufB, 8)
+    GW_FUSED_LAYER(5, bufB, bufA, 4)
+    GW_FUSED_LAYER(6, bufA, bufB, 2)
+    GW_FUSED_LAYER(7, bufB, bufA, 1)
+    GW_FUSED_LAYER(8, bufA, bufB, 1)
 #undef GW_FUSED_LAYER
+    if (more) {
+      if (!PREFETCH) load_x<IN>(raw, p, nb, nq);
+      store_x<IN>(bufA, raw, nq);
+      __syncthreads();
+    }
+  }
 }
 
 bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,
@@ -955,12 +1197,26 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
   ConvP q = p;
   q.Lin = W;
   q.Ci = C[0];
-  const int64_t blocks = (int64_t)p.n * ((W + T - 1) / T);
-  if (blocks > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const int64_t ntile = (int64_t)p.n * ((W + T - 1) / T);
+  if (ntile > (int64_t)1 << 30) return hipErrorInvalidValue;
+  // one resident grid: (blocks per CU) x CUs, at most one block per tile
+  static int occ[2] = {0, 0}, cus = 0;
+  const int v = ring ? 1 : 0;
+  if (!occ[v]) {
+    int dev = 0, n = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = ring ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dc_fused<IN_RING>, NTHR, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dc_fused<IN_F32>, NTHR, 0);
+    if (e != hipSuccess) return e;
+    occ[v] = n > 0 ? n : 1;
+  }
+  const int64_t grid = std::min<int64_t>(ntile, (int64_t)occ[v] * cus);
   if (ring)
-    hipLaunchKernelGGL(dc_fused<IN_RING>, dim3((unsigned)blocks), dim3(NTHR), 0, st, q, f);
+    hipLaunchKernelGGL(dc_fused<IN_RING>, dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
   else
-    hipLaunchKernelGGL(dc_fused<IN_F32>, dim3((unsigned)blocks), dim3(NTHR), 0, st, q, f);
+    hipLaunchKernelGGL(dc_fused<IN_F32>, dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
   return hipGetLastError();
 }
 
