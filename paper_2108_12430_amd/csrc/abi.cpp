@@ -1229,6 +1229,10 @@ extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float
 // BBHnet
 // ===========================================================================
 namespace {
+// partial sums per window of the pooled last BBHnet stage (column tiles x
+// channel shares; 16 for 2048-sample windows)
+constexpr int kGapParts = 256;
+
 struct BbWs {
   size_t gath = NONE, h = 0, o[2] = {0, 0}, gap = 0, total = 0;
 };
@@ -1252,7 +1256,7 @@ int bb_layout(const gw_model* m, int n, int W, bool pool, int precision, BbWs& b
   b.h = take(mh);
   b.o[0] = take(mh);
   b.o[1] = take(mh);
-  b.gap = take((size_t)n * 64 * sizeof(float));
+  b.gap = take((size_t)n * kGapParts * sizeof(float));
   b.total = off;
   return GW_OK;
 }
@@ -1367,8 +1371,8 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       int epi_b = gw::EPI_RESID_RELU;
       if (last) {
         // last stage: the pooling head is fused into the epilogue
-        const int nblk = (Lo + gw::conv_bf16_col_tile(sd.co, false) - 1) / gw::conv_bf16_col_tile(sd.co, false);
-        if (nblk > 64) return fail(GW_EUNSUPPORTED, "window too long for the fused pooling head");
+        const int nblk = gw::conv_bf16_gap_parts(sd.co, Lo);
+        if (nblk < 1 || nblk > kGapParts) return fail(GW_EUNSUPPORTED, "window too long for the fused pooling head");
         pb.hw = P + m->head_w;
         pb.gap_part = reinterpret_cast<float*>(wsb + b.gap);
         epi_b = gw::EPI_RESID_GAP;
@@ -1378,7 +1382,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       LAUNCH(nm("bbh_conva_bf16", "S", s), st, gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
       LAUNCH(nm("bbh_convb_bf16", "S", s), st, gw::launch_conv_bf16(pb, false, epi_b, gw::SRC_DENSE, st));
       if (last) {
-        const int nblk = (Lo + gw::conv_bf16_col_tile(sd.co, false) - 1) / gw::conv_bf16_col_tile(sd.co, false);
+        const int nblk = gw::conv_bf16_gap_parts(sd.co, Lo);
         LAUNCH("gap_finalize", st,
                gw::launch_gap_finalize(pb.gap_part, nblk, P + m->head_b, logits, n, Lo, st));
       }

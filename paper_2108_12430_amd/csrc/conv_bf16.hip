@@ -271,17 +271,27 @@ __device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROW
 
 // Shortcut tile for the residual stage: row c holds the stage input at
 // position 2 (col0 + c) (1x1 kernel, stride 2), channel-minor.
-template <int CSP, int TN, int RSX, bool XS_F32>
-__device__ __forceinline__ void stage_shortcut(uint16_t* xt, const ConvP& p, int b, int col0) {
+template <int CSP, int TN>
+struct ShortRaw {
+  static constexpr int ITEMS = ((TN / 4) * CSP + 255) / 256;  // (channel, 4-row chunk) items per thread
+  uint32_t v[ITEMS > 0 ? ITEMS : 1][2];                        // four bf16 per item
+};
+
+// Issue the loads of the shortcut tile (row c = stage input at position
+// 2 (col0 + c), channel-minor) into registers; stored by store_shortcut.
+template <int CSP, int TN, bool XS_F32>
+__device__ __forceinline__ void load_shortcut(ShortRaw<CSP, TN>& R, const ConvP& p, int b, int col0) {
   const int Cs = p.Cs, Ls = p.Ls;
   const int p0 = 2 * col0;  // multiple of 8
   const bool vec = (Ls & 7) == 0 &&
                    ((XS_F32 ? reinterpret_cast<uintptr_t>(p.xs) : reinterpret_cast<uintptr_t>(p.xsh)) & 15) == 0;
-  for (int e = threadIdx.x; e < (TN / 4) * CSP; e += 256) {
+#pragma unroll
+  for (int it = 0; it < ShortRaw<CSP, TN>::ITEMS; ++it) {
+    const int e = threadIdx.x + 256 * it;
     const int i = e % CSP, ch = e / CSP;
     const int pc = p0 + 8 * ch;  // positions pc .. pc+7 -> rows 4ch .. 4ch+3 (even positions)
-    uint16_t v[4] = {0, 0, 0, 0};
-    if (i < Cs) {
+    uint32_t v[4] = {0, 0, 0, 0};
+    if (ch < TN / 4 && i < Cs) {
       const int64_t base = ((int64_t)b * Cs + i) * Ls;
       if (vec && pc + 8 <= Ls) {
         if (XS_F32) {
@@ -300,8 +310,22 @@ __device__ __forceinline__ void stage_shortcut(uint16_t* xt, const ConvP& p, int
         }
       }
     }
+    R.v[it][0] = v[0] | (v[1] << 16);
+    R.v[it][1] = v[2] | (v[3] << 16);
+  }
+}
+
+template <int CSP, int TN, int RSX>
+__device__ __forceinline__ void store_shortcut(uint16_t* xt, const ShortRaw<CSP, TN>& R) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xt[(4 * ch + k) * RSX + i] = v[k];
+  for (int it = 0; it < ShortRaw<CSP, TN>::ITEMS; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    const int i = e % CSP, ch = e / CSP;
+    if (ch >= TN / 4) continue;
+    xt[(4 * ch + 0) * RSX + i] = R.v[it][0] & 0xffff;
+    xt[(4 * ch + 1) * RSX + i] = R.v[it][0] >> 16;
+    xt[(4 * ch + 2) * RSX + i] = R.v[it][1] & 0xffff;
+    xt[(4 * ch + 3) * RSX + i] = R.v[it][1] >> 16;
   }
   for (int e = threadIdx.x; e < RSX; e += 256) xt[TN * RSX + e] = 0;
 }
@@ -317,40 +341,50 @@ __device__ __forceinline__ void stage_shortcut(uint16_t* xt, const ConvP& p, int
 // added to the same accumulators as extra K steps.
 // ---------------------------------------------------------------------------
 template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32,
-          int CSP>
+          int CSP, int MS>
 __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
+  static_assert(MT % MS == 0, "the m-split divides the output-channel tiles");
+  constexpr int MTB = MT / MS;  // output-channel tiles of this block
   constexpr int TN = 64 * NTW;
   constexpr int ROWS = SC * (TN - 1) + KT;
   constexpr int RS = CIP + 8;  // LDS row stride in bf16 (16-byte multiple, skews banks)
   constexpr int KS = (KT * CIP + 31) / 32;
   constexpr int RSX = CSP + 8;
   constexpr int KS2 = (CSP + 31) / 32;
-  constexpr int NFRAG = NPH * MT * KS;
+  constexpr int NFRAG = NPH * MTB * KS;  // weight fragments of this block's channel tiles
   constexpr int TNO = NPH * TN;
   constexpr bool OTILE = EPI != EPI_OUT && EPI != EPI_RESID_GAP && !OUT_F32;
   // the input tile's LDS is reused for the BF16 output tile [C_out][NPH*TN]
-  constexpr int TILE = (ROWS + 1) * RS > 16 * MT * TNO ? (ROWS + 1) * RS : 16 * MT * TNO;
+  constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * TNO ? (ROWS + 1) * RS : 16 * MTB * TNO;
   // weights staged in LDS once per block when they fit beside the tile; only
   // then is the next tile prefetched (LDS reads do not wait on global loads)
   constexpr bool ALDS = 2 * TILE + NFRAG * 1024 <= 80 * 1024;
   __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
   __shared__ __attribute__((aligned(16))) uint16_t xt[CSP > 0 ? (TN + 1) * RSX : 8];
   __shared__ __attribute__((aligned(16))) uint4 alds[ALDS ? NFRAG * 64 : 1];
-  __shared__ float cst[2][16 * MT];
+  __shared__ float cst[2][16 * MTB];
   __shared__ float wsum[4];
 
+  // block j computes output-channel tiles [ms MTB, (ms + 1) MTB), ms = j mod MS,
+  // of the column tiles j / MS, j / MS + gridDim.x / MS, ... (gridDim.x is a
+  // multiple of MS)
+  const int ms = (int)blockIdx.x % MS, bi = (int)blockIdx.x / MS, G = (int)gridDim.x / MS;
+  const int o_lo = 16 * MTB * ms;  // first output channel of this block
   const int tiles_per = (ncol + TN - 1) / TN;
   const int total = tiles_per * p.n;
-  if ((int)blockIdx.x >= total) return;
+  if (bi >= total) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lg = lane >> 4;
   const uint4* wp = reinterpret_cast<const uint4*>(p.wpk);
 
   if (ALDS)
-    for (int e = threadIdx.x; e < (ALDS ? NFRAG * 64 : 0); e += 256) alds[e] = wp[e];
+    for (int e = threadIdx.x; e < (ALDS ? NFRAG * 64 : 0); e += 256) {
+      const int f = e >> 6, ks = f % KS, r = f / KS, mtb = r % MTB, ph = r / MTB;
+      alds[e] = wp[((ph * MT + ms * MTB + mtb) * KS + ks) * 64 + (e & 63)];
+    }
   // per-channel epilogue constants: cst[0] multiplies, cst[1] adds
-  for (int o = threadIdx.x; o < 16 * MT; o += 256) {
-    const int oc = min(o, p.Co - 1);
+  for (int o = threadIdx.x; o < 16 * MTB; o += 256) {
+    const int oc = min(o_lo + o, p.Co - 1);
     float a = 0.f, c = 0.f;
     if (EPI == EPI_AFFINE || EPI == EPI_OUT || EPI == EPI_AFFINE_TANH) {
       a = p.scale[oc];
@@ -366,42 +400,47 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   }
 
   InRaw<CIP, ROWS, IN> raw;
-  {
-    const int t = blockIdx.x;
-    load_input<CIP, ROWS, IN>(raw, p, t / tiles_per, SC * ((t % tiles_per) * TN) - padc);
-  }
+  ShortRaw<CSP, TN> sraw;
+  load_input<CIP, ROWS, IN>(raw, p, bi / tiles_per, SC * ((bi % tiles_per) * TN) - padc);
+  if (CSP > 0) load_shortcut<CSP, TN, XS_F32>(sraw, p, bi / tiles_per, (bi % tiles_per) * TN);
   // ALDS: persistent loop over tiles with prefetch; otherwise one tile per block
-  const int tstep = ALDS ? (int)gridDim.x : total;
-  for (int t = blockIdx.x; t < total; t += tstep) {
+  const int tstep = ALDS ? G : total;
+  for (int t = bi; t < total; t += tstep) {
     const int b = t / tiles_per;
     const int col0 = (t % tiles_per) * TN;
     store_input<CIP, ROWS, RS, IN>(tile, raw, SC * col0 - padc);
-    if (CSP > 0) stage_shortcut<CSP, TN, RSX, XS_F32>(xt, p, b, col0);
+    if (CSP > 0) store_shortcut<CSP, TN, RSX>(xt, sraw);
     __syncthreads();
     if (ALDS) {
       const int tn = t + tstep;
-      if (tn < total) load_input<CIP, ROWS, IN>(raw, p, tn / tiles_per, SC * ((tn % tiles_per) * TN) - padc);
+      if (tn < total) {
+        load_input<CIP, ROWS, IN>(raw, p, tn / tiles_per, SC * ((tn % tiles_per) * TN) - padc);
+        if (CSP > 0) load_shortcut<CSP, TN, XS_F32>(sraw, p, tn / tiles_per, (tn % tiles_per) * TN);
+      }
     }
 
-    f32x4 acc[NTW][NPH][MT];
+    f32x4 acc[NTW][NPH][MTB];
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
       for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < MTB; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-#pragma unroll 1
+    // few accumulators: unroll so the next K steps' LDS reads are in flight
+    // during this step's MFMAs; many accumulators: keep the loop rolled
+    constexpr int KUNROLL = NTW * NPH * MTB <= 2 ? 4 : 1;
+#pragma unroll KUNROLL
     for (int ks = 0; ks < KS; ++ks) {
       const int kappa = 32 * ks + 8 * lg;
       const int jj = kappa / CIP, i0 = kappa - jj * CIP;
-      uint4 af[NPH][MT];
+      uint4 af[NPH][MTB];
 #pragma unroll
       for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          af[ph][mt] = ALDS ? alds[ALDS ? ((ph * MT + mt) * KS + ks) * 64 + lane : 0]
-                            : wp[((ph * MT + mt) * KS + ks) * 64 + lane];
+        for (int mt = 0; mt < MTB; ++mt)
+          af[ph][mt] = ALDS ? alds[ALDS ? ((ph * MTB + mt) * KS + ks) * 64 + lane : 0]
+                            : wp[((ph * MT + ms * MTB + mt) * KS + ks) * 64 + lane];
 #pragma unroll
       for (int nt = 0; nt < NTW; ++nt) {
         const int c = (wave * NTW + nt) * 16 + lc;
@@ -411,7 +450,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
 #pragma unroll
         for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
+          for (int mt = 0; mt < MTB; ++mt)
             acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                 __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
       }
@@ -420,9 +459,9 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
       const uint4* sp = reinterpret_cast<const uint4*>(p.wspk);
       for (int ks = 0; ks < KS2; ++ks) {
         const int kappa = 32 * ks + 8 * lg;
-        uint4 af[MT];
+        uint4 af[MTB];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) af[mt] = sp[(mt * KS2 + ks) * 64 + lane];
+        for (int mt = 0; mt < MTB; ++mt) af[mt] = sp[((ms * MTB + mt) * KS2 + ks) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
           const int c = (wave * NTW + nt) * 16 + lc;
@@ -430,7 +469,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
           const uint4 bv = *reinterpret_cast<const uint4*>(&xt[row * RSX + (kappa < CSP ? kappa : 0)]);
           const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
+          for (int mt = 0; mt < MTB; ++mt)
             acc[nt][0][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[mt]), bb,
                                                                      acc[nt][0][mt], 0, 0, 0);
         }
@@ -446,12 +485,12 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
       const int col = col0 + (wave * NTW + nt) * 16 + lc;
       if (col >= ncol) continue;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int o = 16 * mt + 4 * lg + r;
+          const int ol = 16 * mt + 4 * lg + r, o = o_lo + ol;  // block-local, global channel
           if (o >= p.Co) continue;
-          const float ka = cst[0][o], kb = cst[1][o];
+          const float ka = cst[0][ol], kb = cst[1][ol];
           float v[NPH];
 #pragma unroll
           for (int ph = 0; ph < NPH; ++ph) {
@@ -492,7 +531,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
             }
           } else {
 #pragma unroll
-            for (int ph = 0; ph < NPH; ++ph) otile[o * TNO + NPH * (col - col0) + ph] = bf16_rne(v[ph]);
+            for (int ph = 0; ph < NPH; ++ph) otile[ol * TNO + NPH * (col - col0) + ph] = bf16_rne(v[ph]);
           }
         }
     }
@@ -501,9 +540,10 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
       __syncthreads();
       const int Co = p.Co, Lout = p.Lout;
       const int u00 = NPH * col0;
-      uint16_t* yb = p.yh + (int64_t)b * Co * Lout;
+      const int nco = min(Co - o_lo, 16 * MTB);  // this block's channels
+      uint16_t* yb = p.yh + ((int64_t)b * Co + o_lo) * Lout;
       const bool vec = (Lout & 7) == 0 && (reinterpret_cast<uintptr_t>(p.yh) & 15) == 0;
-      for (int e = threadIdx.x; e < Co * (TNO / 8); e += 256) {
+      for (int e = threadIdx.x; e < nco * (TNO / 8); e += 256) {
         const int o = e / (TNO / 8), cu = e - o * (TNO / 8);
         const int u0 = u00 + 8 * cu;
         if (u0 >= Lout) continue;
@@ -521,7 +561,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
       if (lane == 0) wsum[wave] = gsum;
       __syncthreads();
       if (threadIdx.x == 0)
-        p.gap_part[(int64_t)b * tiles_per + (t % tiles_per)] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+        p.gap_part[((int64_t)b * tiles_per + (t % tiles_per)) * MS + ms] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
     }
     __syncthreads();  // LDS tiles are rewritten by the next iteration
   }
@@ -534,19 +574,19 @@ struct Key {
   int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32, csp;
 };
 
-template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32, int CSP>
+template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32, int CSP, int NTW,
+          int MS>
 static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
-  constexpr int NTW = (NPH * MT <= 4) ? 4 : 2;
-  constexpr int TN = 64 * NTW;
+  constexpr int TN = 64 * NTW, MTB = MT / MS;
   // same test as the kernel's ALDS: persistent grid only when weights fit in LDS
   constexpr int ROWS = SC * (TN - 1) + KT, RS = CIP + 8, KS = (KT * CIP + 31) / 32;
-  constexpr int TILE = (ROWS + 1) * RS > 16 * MT * NPH * TN ? (ROWS + 1) * RS : 16 * MT * NPH * TN;
-  constexpr bool ALDS = 2 * TILE + NPH * MT * KS * 1024 <= 80 * 1024;
-  auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP>;
+  constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * NPH * TN ? (ROWS + 1) * RS : 16 * MTB * NPH * TN;
+  constexpr bool ALDS = 2 * TILE + NPH * MTB * KS * 1024 <= 80 * 1024;
+  auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP, MS>;
   const int64_t tiles = (int64_t)((g.ncol + TN - 1) / TN) * p.n;
-  if (tiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+  if (tiles * MS > (int64_t)1 << 30) return hipErrorInvalidValue;
   if (!ALDS) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(256), 0, st, p, g.padc, g.ncol);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * MS)), dim3(256), 0, st, p, g.padc, g.ncol);
     return hipGetLastError();
   }
   // persistent grid: enough blocks to fill every CU at the kernel's occupancy
@@ -559,51 +599,62 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
       cus = 256;
     max_blocks = per_cu * cus;
   }
-  const int blocks = (int)std::min<int64_t>(tiles, max_blocks);
+  // a multiple of MS blocks: each channel share walks the same column tiles
+  const int blocks = (int)std::min<int64_t>(tiles, std::max(max_blocks / MS, 1)) * MS;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, p, g.padc, g.ncol);
   return hipGetLastError();
 }
 
-// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32, CSP) of every compiled variant.
-#define GW_BF16_VARIANTS(X)                                                  \
-  /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */     \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0)               \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0)              \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0)                \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0)               \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)               \
-  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
-  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
-  /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */               \
-  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
-  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
-  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)              \
-  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0)               \
-  /* output conv k7 s1 with causal slice + subtraction */                   \
-  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false, 0)                        \
-  /* BBHnet-shaped stages: conv_a, then conv_b + 1x1 stride-2 shortcut */    \
-  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0)                       \
-  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8)                \
-  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0)                     \
-  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32)              \
-  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0)                     \
-  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64)             \
-  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64)            \
-  /* training forward (BF16 conv variant): FP32 activations in, FP32 z out */ \
-  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                       \
-  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                      \
-  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0)                       \
-  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0)                        \
-  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0)
+// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32, CSP, NTW, MS) of every
+// compiled variant: NTW 16-column tiles per wave (a block covers 64 NTW
+// columns) and an m-split MS (a block computes MT / MS output-channel tiles).
+// The BBHnet layers are small GEMMs whose weights outweigh a window's
+// activations: each block keeps one output-channel tile's weights in LDS and
+// streams narrow column tiles past them.
+#define GW_BF16_VARIANTS(X)                                                         \
+  /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */            \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1)                \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1)               \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1)                 \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1)                \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)                \
+  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */                      \
+  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)                \
+  /* output conv k7 s1 with causal slice + subtraction */                          \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false, 0, 4, 1)                         \
+  /* BBHnet-shaped stages: conv_a, then conv_b + 1x1 stride-2 shortcut */           \
+  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0, 1, 2)                        \
+  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8, 1, 2)                 \
+  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 4)                      \
+  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32, 1, 4)               \
+  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 8)                      \
+  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64, 1, 8)               \
+  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64, 1, 8)                \
+  /* training forward (BF16 conv variant): FP32 activations in, FP32 z out */      \
+  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                         \
+  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
+  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                         \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1)                          \
+  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1)
 
-int conv_bf16_col_tile(int Co, bool tr) {
-  const int nph = tr ? 2 : 1, mt = (Co + 15) / 16;
-  return 64 * ((nph * mt <= 4) ? 4 : 2);
+int conv_bf16_gap_parts(int Co, int Lout) {
+  // partial sums per window written by the pooled (EPI_RESID_GAP) variant
+  const int mt = (Co + 15) / 16;
+#define GW_GAP(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS) \
+  if (EPI == EPI_RESID_GAP && mt == MT) return (Lout + 64 * NTW - 1) / (64 * NTW) * MS;
+  GW_BF16_VARIANTS(GW_GAP)
+#undef GW_GAP
+  return -1;
 }
 
 bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
@@ -612,7 +663,7 @@ bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
   if (tr && stride != 2) return false;
   const Geo g = make_geo(tr, k, stride, 3, 1 << 20);
   const int cip = cip_of(Ci), mt = (Co + 15) / 16;
-#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS) \
+#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS) \
   if (cip == CIP && mt == MT && g.nph == NPH && g.kt == KT && g.sc == SC) return true;
   GW_BF16_VARIANTS(GW_SHAPE)
 #undef GW_SHAPE
@@ -640,10 +691,10 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
   k.csp = res ? cip_of(p.Cs) : 0;
   if (res && (!p.wspk || p.Ls != 2 * p.Lout)) return hipErrorInvalidValue;
   if (epi == EPI_RESID_GAP && (!p.hw || !p.gap_part)) return hipErrorInvalidValue;
-#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS)                                     \
+#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS)                            \
   if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
       k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF && k.csp == CS)                 \
-    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS>(p, g, st);
+    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS>(p, g, st);
   GW_BF16_VARIANTS(GW_LAUNCH)
 #undef GW_LAUNCH
   return hipErrorNotSupported;
@@ -754,9 +805,14 @@ __host__ __device__ constexpr int koff(int l, int lg, int ks) {
 }
 // the (phase, channel tile) pairs of a layer with few column groups are
 // split over SPL waves
+#ifndef GW_FUSED_MAXSPL
+#define GW_FUSED_MAXSPL 4
+#endif
 constexpr int SPL(int l) {
   return COMPACT(l) ? 1
-         : NPH(l) * MT(l) % 4 == 0 && NG(l) * 4 <= NW ? 4 : (NPH(l) * MT(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
+         : GW_FUSED_MAXSPL >= 4 && NPH(l) * MT(l) % 4 == 0 && NG(l) * 4 <= NW
+             ? 4
+             : (GW_FUSED_MAXSPL >= 2 && NPH(l) * MT(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
 }
 }  // namespace fused
 
