@@ -1,0 +1,123 @@
+"""Parity at the serving benchmark's full size and launch configuration.
+
+One step of the closed-loop mix: 179 DeepClean streams (21 x 32768 at
+4096 Hz) and 77 BBHnet streams (2 x 2048 at 2048 Hz) resident in one pool,
+strides drawn per stream from {1/16, 1/8, 1/4} s.  Every DeepClean window
+goes through one batched BF16 call (the fused kernel, 179 windows in one
+launch) and every BBHnet window through one batched BF16 call, as the
+benchmark times them.  A sample of the windows is checked against the FP64
+oracle (normwise error <= 2e-2, the BF16 bound); every output is checked
+for finiteness; a second identical call must agree bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2108_12430_amd import gwstream as gs
+from paper_2108_12430_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+BF16_TOL = 2e-2
+N_DC, N_BB = 179, 77
+DC_C, DC_W, DC_FS = 21, 32768, 4096
+BB_C, BB_W, BB_FS = 2, 2048, 2048
+SAMPLE = 16
+
+
+def rel(a, r):
+    a = np.asarray(a, np.float64)
+    r = np.asarray(r, np.float64)
+    return float(np.max(np.abs(a - r)) / np.max(np.abs(r)))
+
+
+def strides_mix(seed=6):
+    rng = np.random.default_rng(seed)
+    frac = np.array([1 / 16, 1 / 8, 1 / 4])
+    dc_s = (rng.choice(frac, N_DC) * DC_FS).astype(np.int64)
+    bb_s = (rng.choice(frac, N_BB) * BB_FS).astype(np.int64)
+    return dc_s, bb_s
+
+
+def fill(pool, slot, data, s, W):
+    """Advance a ring by a full window, then by one stride of s samples:
+    the snapshot is data[:, s : s + W]."""
+    C = data.shape[0]
+    pool.update([slot], [W], torch.from_numpy(np.ascontiguousarray(data[:, :W]).reshape(-1)).to(DEV), [0])
+    pool.update([slot], [s], torch.from_numpy(np.ascontiguousarray(data[:, W:W + s]).reshape(-1)).to(DEV), [0])
+    assert data.shape == (C, W + s)
+
+
+@pytest.fixture(scope="module")
+def mix():
+    dc_s, bb_s = strides_mix()
+    per_dc = DC_C * DC_W * 6 + 1024
+    per_bb = BB_C * BB_W * 6 + 1024
+    pool = gs.Pool(N_DC * per_dc + N_BB * per_bb + (8 << 20), max_slots=N_DC + N_BB, max_items=N_DC + N_BB)
+    dc_slots = [pool.open(DC_C, DC_W) for _ in range(N_DC)]
+    bb_slots = [pool.open(BB_C, BB_W) for _ in range(N_BB)]
+    pick_dc = set(np.linspace(0, N_DC - 1, SAMPLE).astype(int).tolist())
+    pick_bb = set(np.linspace(0, N_BB - 1, SAMPLE).astype(int).tolist())
+    keep_dc, keep_bb, strain = {}, {}, []
+    for i in range(N_DC):
+        s = int(dc_s[i])
+        wit, st = synth.witness_stream(1000 + i, DC_W + s) if i in pick_dc else \
+            (synth.gaussian(1000 + i, (DC_C, DC_W + s)), synth.gaussian(5000 + i, (DC_W + s,)))
+        fill(pool, dc_slots[i], wit.astype(np.float32), s, DC_W)
+        strain.append(st[DC_W:DC_W + s].astype(np.float32))
+        if i in pick_dc:
+            keep_dc[i] = (wit[:, s:s + DC_W], st[DC_W:DC_W + s])
+    for i in range(N_BB):
+        s = int(bb_s[i])
+        x = synth.gaussian(3000 + i, (BB_C, BB_W + s))
+        fill(pool, bb_slots[i], x.astype(np.float32), s, BB_W)
+        if i in pick_bb:
+            keep_bb[i] = x[:, s:s + BB_W]
+    torch.cuda.synchronize()
+    dcm = gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(DEV), synth.deepclean_layers())
+    bbm = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(DEV), synth.bbhnet_stages())
+    return dict(pool=pool, dc_s=dc_s, bb_s=bb_s, dc_slots=dc_slots, bb_slots=bb_slots, keep_dc=keep_dc,
+                keep_bb=keep_bb, strain=torch.from_numpy(np.concatenate(strain)).to(DEV), dcm=dcm, bbm=bbm)
+
+
+def test_deepclean_bench_launch(mix):
+    pool, dc_s, dcm = mix["pool"], mix["dc_s"], mix["dcm"]
+    n = N_DC
+    noise = torch.empty((n, DC_W), device=DEV)
+    clean = torch.empty(int(dc_s.sum()), device=DEV)
+    clean2 = torch.empty_like(clean)
+    ws = torch.empty(dcm.workspace_bytes(n, DC_W, gs.BF16), dtype=torch.uint8, device=DEV)
+    dcm.forward(pool=pool, slots=mix["dc_slots"], W=DC_W, strides=dc_s, strain=mix["strain"], clean=clean,
+                noise=noise, precision=gs.BF16, ws=ws)
+    # the benchmark's call (no noise output) gives the same clean output bitwise
+    dcm.forward(pool=pool, slots=mix["dc_slots"], W=DC_W, strides=dc_s, strain=mix["strain"], clean=clean2,
+                precision=gs.BF16, ws=ws)
+    torch.cuda.synchronize()
+    got_n, got_c = noise.cpu().numpy(), clean.cpu().numpy()
+    assert np.isfinite(got_n).all() and np.isfinite(got_c).all()
+    assert np.array_equal(got_c, clean2.cpu().numpy())
+    params, layers = synth.deepclean_params(0), synth.deepclean_layers()
+    offs = np.concatenate([[0], np.cumsum(dc_s)])
+    for i, (x, st) in mix["keep_dc"].items():
+        en = ref.deepclean_forward(params, x[None], layers)
+        assert rel(got_n[i], en[0]) <= BF16_TOL, i
+        _, ec = ref.causal_clean(en, st[None])
+        assert rel(got_c[offs[i]:offs[i + 1]], ec[0]) <= BF16_TOL, i
+
+
+def test_bbhnet_bench_launch(mix):
+    pool, bbm = mix["pool"], mix["bbm"]
+    n = N_BB
+    logits = torch.empty(n, device=DEV)
+    logits2 = torch.empty(n, device=DEV)
+    ws = torch.empty(bbm.workspace_bytes(n, BB_W, gs.BF16), dtype=torch.uint8, device=DEV)
+    bbm.forward(pool=pool, slots=mix["bb_slots"], W=BB_W, logits=logits, precision=gs.BF16, ws=ws)
+    bbm.forward(pool=pool, slots=mix["bb_slots"], W=BB_W, logits=logits2, precision=gs.BF16, ws=ws)
+    torch.cuda.synchronize()
+    got = logits.cpu().numpy()
+    assert np.isfinite(got).all()
+    assert np.array_equal(got, logits2.cpu().numpy())
+    idx = sorted(mix["keep_bb"])
+    exp = ref.bbhnet_forward(synth.bbhnet_params(0), np.stack([mix["keep_bb"][i] for i in idx]))
+    assert rel(got[idx], exp) <= BF16_TOL
