@@ -12,6 +12,11 @@ arrive while earlier steps are still running are admitted into the next step
 refuses a new stream (GW_ENOMEM) it waits in an admission queue until another
 stream closes.
 
+Requests and their bookkeeping form no reference cycles, so a latency-critical
+caller can freeze and disable Python's cyclic garbage collector around the
+loop (the benchmark does): its full passes otherwise stall the loop for tens
+of milliseconds once many objects are alive.
+
 The loop is written against a small executor interface so that its host
 logic (admission, ordering, grouping, latency accounting) can be exercised
 without a GPU; ``HipExecutor`` is the device implementation and the only one
@@ -76,6 +81,9 @@ class Server:
         self.completed: List[Request] = []
         self._next_sid = 0
         self.steps = 0
+        self._npending = 0
+        self._ready: Dict[int, None] = {}  # streams with pending requests, in order of first arrival
+        self._closing: Dict[int, None] = {}
 
     # ---- stream lifecycle ------------------------------------------------
     def open_stream(self, model: str, C: int, W: int) -> int:
@@ -94,6 +102,7 @@ class Server:
         """Close after the stream's queued requests have completed."""
         st = self.streams[sid]
         st.closing = True
+        self._closing[sid] = None
         self._reap_closed()
 
     def _admit(self) -> None:
@@ -107,15 +116,16 @@ class Server:
 
     def _reap_closed(self) -> None:
         freed = False
-        for sid in list(self.streams):
+        for sid in list(self._closing):
             st = self.streams[sid]
-            if st.closing and not st.pending and st.done_seq == st.next_seq:
+            if not st.pending and st.done_seq == st.next_seq:
                 if st.slot is not None:
                     self.ex.close(st.slot)
                     freed = True
                 elif sid in self.admission:
                     self.admission.remove(sid)
                 del self.streams[sid]
+                del self._closing[sid]
         if freed:
             self._admit()
 
@@ -135,10 +145,13 @@ class Server:
         r = Request(sid, samples, strain, self.clock() if t_arrival is None else t_arrival, st.next_seq)
         st.next_seq += 1
         st.pending.append(r)
+        self._npending += 1
+        if sid not in self._ready:
+            self._ready[sid] = None
         return r
 
     def pending(self) -> int:
-        return sum(len(s.pending) for s in self.streams.values())
+        return self._npending
 
     # ---- the loop ----------------------------------------------------------
     def step(self) -> int:
@@ -148,10 +161,14 @@ class Server:
         while len(self.inflight) >= self.max_inflight:
             self._complete_oldest(block=True)
         groups: Dict[Tuple[str, int, int], List[Tuple[int, Request]]] = collections.OrderedDict()
-        for st in self.streams.values():
-            if st.slot is None or not st.pending:
-                continue
+        for sid in list(self._ready):
+            st = self.streams[sid]
+            if st.slot is None:
+                continue  # not admitted yet
             r = st.pending.popleft()
+            self._npending -= 1
+            if not st.pending:
+                del self._ready[sid]
             groups.setdefault((st.model, st.C, st.W), []).append((st.slot, r))
         n = 0
         for (model, C, W), items in groups.items():
@@ -255,27 +272,33 @@ class HipExecutor:
 
     def _buf(self, key, n_f, n_s, n_out):
         """Next buffer set of a group with room for n_f samples, n_s strain
-        values and n_out outputs (grown by doubling when too small)."""
+        values and n_out outputs.  All RING sets of a group share one
+        capacity and are (re)allocated together, doubling when too small, so
+        pinned host allocations happen on the first steps rather than
+        whenever a ring entry is first used."""
         torch = self.torch
         ring = self.bufs.setdefault(key, [None] * self.RING)
+        cap = ring[0]["cap"] if ring[0] is not None else [0, 0, 0]
+        need = [n_f, n_s, n_out]
+        if any(n > c for n, c in zip(need, cap)):
+            cap = [max(n, 2 * c, 1) if n > c else c for n, c in zip(need, cap)]
+            for b in ring:
+                if b is not None and b["ev"] is not None:
+                    b["ev"].synchronize()
+            with torch.cuda.stream(self._stream(key)):
+                for i in range(self.RING):
+                    ring[i] = {"cap": cap, "ev": None,
+                               "h_x": torch.empty(cap[0], dtype=torch.float32, pin_memory=True),
+                               "h_s": torch.empty(cap[1], dtype=torch.float32, pin_memory=True),
+                               "h_o": torch.empty(cap[2], dtype=torch.float32, pin_memory=True),
+                               "d_x": torch.empty(cap[0], dtype=torch.float32, device=self.dev),
+                               "d_s": torch.empty(cap[1], dtype=torch.float32, device=self.dev),
+                               "d_o": torch.empty(cap[2], dtype=torch.float32, device=self.dev)}
         k = self.next_buf.get(key, 0)
         self.next_buf[key] = (k + 1) % self.RING
         b = ring[k]
-        if b is not None and b["ev"] is not None:
+        if b["ev"] is not None:
             b["ev"].synchronize()
-        if b is None or b["cap"][0] < n_f or b["cap"][1] < n_s or b["cap"][2] < n_out:
-            cap = [max(n_f, 1), max(n_s, 1), max(n_out, 1)]
-            if b is not None:
-                cap = [max(c, 2 * o) if c > o else o for c, o in zip(cap, b["cap"])]
-            with torch.cuda.stream(self._stream(key)):
-                b = {"cap": cap,
-                     "h_x": torch.empty(cap[0], dtype=torch.float32, pin_memory=True),
-                     "h_s": torch.empty(cap[1], dtype=torch.float32, pin_memory=True),
-                     "h_o": torch.empty(cap[2], dtype=torch.float32, pin_memory=True),
-                     "d_x": torch.empty(cap[0], dtype=torch.float32, device=self.dev),
-                     "d_s": torch.empty(cap[1], dtype=torch.float32, device=self.dev),
-                     "d_o": torch.empty(cap[2], dtype=torch.float32, device=self.dev)}
-            ring[k] = b
         b["ev"] = None
         return b
 
@@ -294,15 +317,10 @@ class HipExecutor:
         s_tot = int(strides.sum())
         n_out = s_tot if is_dc else len(items)
         b = self._buf(key, n_f, s_tot if is_dc else 0, n_out)
-        hv = b["h_x"].numpy()
-        for (_, r), o, sz in zip(items, offsets, sizes):
-            hv[o:o + sz] = r.samples.reshape(-1)
+        np.concatenate([r.samples.reshape(-1) for _, r in items], out=b["h_x"].numpy()[:n_f])
         if is_dc:
-            sv = b["h_s"].numpy()
-            o = 0
-            for (_, r), s in zip(items, strides):
-                sv[o:o + s] = r.strain if r.strain is not None else 0.0
-                o += s
+            np.concatenate([r.strain if r.strain is not None else np.zeros(r.samples.shape[1], np.float32)
+                            for _, r in items], out=b["h_s"].numpy()[:s_tot])
         ws = self._ws(key, len(items))
         with torch.cuda.stream(st):
             dx = b["d_x"][:n_f]
