@@ -142,9 +142,28 @@ def cpu_baseline(dc_s, bb_s, budget_s=12.0):
         i += 1
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    # the same requests on one core
+    from threadpoolctl import threadpool_limits
+    n1 = s1 = 0
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < budget_s / 2 or n1 < 2:
+            i = n1
+            if i % 2 == 0:
+                s = int(dc_s[(i // 2) % N_DC])
+                x = ref.snapshot_after(wit, DC_W + s, DC_W)[None]
+                ref.causal_clean(ref.deepclean_forward(dcp, x), strain[None, DC_W: DC_W + s])
+            else:
+                s = int(bb_s[(i // 2) % N_BB])
+                ref.bbhnet_forward(bbp, ref.snapshot_after(bbx, BB_W + s, BB_W)[None])
+            s1 += s
+            n1 += 1
+        d1 = time.perf_counter() - t1
     return {"value": samples / dt, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_dc} DeepClean + {n_bb} BBHnet requests of the same mix (FP64 numpy oracle, "
-                      f"full-window recompute per request), {dt:.1f} s"}
+                      f"full-window recompute per request), {dt:.1f} s",
+            "single_core": {"value": s1 / d1, "unit": "samples/s",
+                            "sample": f"{n1} requests alternating DeepClean/BBHnet, {d1:.1f} s, 1 thread"}}
 
 
 def traffic_for(kernel):
@@ -164,10 +183,11 @@ def traffic_for(kernel):
     return None if k is None else float(k["bytes_per_launch"])
 
 
-def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True):
+def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True, precision="fp32"):
     """One DeepClean training step = batch-statistics forward, band-passed
-    MSE (55-65 Hz), hand-written backward (FP32); the optimizer update is
-    outside the library and not timed."""
+    MSE (55-65 Hz), hand-written backward (FP32 activations, statistics and
+    gradients; precision "bf16" runs the convolutions on BF16 matrix cores);
+    the optimizer update is outside the library and not timed."""
     import torch
 
     from paper_2108_12430_amd import gwstream as gs
@@ -179,15 +199,16 @@ def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True):
     x = x.to(dev)
     st = torch.from_numpy(np.ascontiguousarray(np.tile(strain.reshape(4, W), (B // 4, 1)))).to(dev)
     flags = gs.TRAIN | (gs.RECOMPUTE if recompute else 0)
+    prec = gs.BF16 if precision == "bf16" else gs.FP32
     noise = torch.empty((B, W), device=dev)
-    ws = torch.empty(m.workspace_bytes(B, W, gs.FP32, flags), dtype=torch.uint8, device=dev)
+    ws = torch.empty(m.workspace_bytes(B, W, prec, flags), dtype=torch.uint8, device=dev)
     scratch = torch.empty(m.backward_scratch_bytes(B, W, flags), dtype=torch.uint8, device=dev)
     dp = torch.empty_like(params)
 
     def one():
-        m.forward(x=x, noise=noise, flags=flags, ws=ws)
+        m.forward(x=x, noise=noise, flags=flags, ws=ws, precision=prec)
         loss, dn = gs.bandpass_mse(st, noise, float(DC_FS), 55.0, 65.0)
-        m.backward(x, dn, ws, dp, flags=flags, scratch=scratch)
+        m.backward(x, dn, ws, dp, flags=flags, scratch=scratch, precision=prec)
 
     for _ in range(warmup):
         one()
@@ -197,8 +218,66 @@ def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True):
         one()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return {"batch": B, "window": W, "ms_per_step": 1e3 * dt, "samples_per_s": B * W / dt, "dtype": "f32",
-            "recompute": recompute, "workspace_MB": (ws.numel() + scratch.numel()) / 1e6}
+    return {"batch": B, "window": W, "ms_per_step": 1e3 * dt, "samples_per_s": B * W / dt,
+            "conv_dtype": precision, "recompute": recompute, "workspace_MB": (ws.numel() + scratch.numel()) / 1e6}
+
+
+def bbhnet_flops(L=BB_W):
+    """Algorithmic FLOPs of one BBHnet window (three residual stages)."""
+    macs = 0
+    for ci, co in ((BB_C, 32), (32, 64), (64, 128)):
+        L //= 2
+        macs += co * L * ci * 7 + co * L * co * 7 + co * L * ci   # conv_a, conv_b, 1x1 shortcut
+    return 2.0 * (macs + 128)
+
+
+def bbhnet_batch_bench(dev, batches=(64, 256, 1024), iters=20):
+    """BBHnet BF16 forward on dense batches of 2 x 2048 windows."""
+    import torch
+
+    from paper_2108_12430_amd import gwstream as gs
+    from paper_2108_12430_amd import synth
+    bb = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(dev), synth.bbhnet_stages())
+    out = []
+    for B in batches:
+        x = torch.from_numpy(synth.bbh_windows(3 + B, B)[0]).to(dev)
+        logits = torch.empty(B, device=dev)
+        ws = torch.empty(bb.workspace_bytes(B, BB_W, gs.BF16), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            bb.forward(x=x, logits=logits, precision=gs.BF16, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            bb.forward(x=x, logits=logits, precision=gs.BF16, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / iters
+        tf = B * bbhnet_flops() / dt / 1e12
+        out.append({"batch": B, "ms": 1e3 * dt, "windows_per_s": B / dt, "samples_per_s": B * BB_W / dt,
+                    "tflops": tf, "frac_of_bf16_peak": tf / BF16_PEAK_TFLOPS})
+    return out
+
+
+def d0_latency(dev, reps=50):
+    """One 1-s window (21 x 4096) through DeepClean, FP32, batch 1:
+    synchronous call latency."""
+    import torch
+
+    from paper_2108_12430_amd import gwstream as gs
+    from paper_2108_12430_amd import synth
+    m = gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(dev), synth.deepclean_layers())
+    x = torch.from_numpy(synth.witness_stream(1, 4096)[0][None]).to(dev)
+    noise = torch.empty((1, 4096), device=dev)
+    ws = torch.empty(m.workspace_bytes(1, 4096, gs.FP32), dtype=torch.uint8, device=dev)
+    lat = []
+    for i in range(reps + 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.forward(x=x, noise=noise, precision=gs.FP32, ws=ws)
+        torch.cuda.synchronize()
+        if i >= 5:
+            lat.append(1e3 * (time.perf_counter() - t0))
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "config": "DeepClean FP32, 21 x 4096 (1 s at 4096 Hz), batch 1"}
 
 
 def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
@@ -283,10 +362,11 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
     out["open_loop"] = []
     for lam in rates:
         per = lam * w / w.sum()   # per-stream Poisson rates proportional to 1/stride
+        span = max(seconds, 1e4 / lam)  # at least 10^4 updates per rate
         arr = []
         for i, r in enumerate(per):
             t = rng.exponential(1.0 / r)
-            while t < seconds:
+            while t < span:
                 arr.append((t, i))
                 t += rng.exponential(1.0 / r)
         arr.sort()
@@ -309,10 +389,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="1000,5000,20000")
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-band", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -540,8 +621,15 @@ def main():
 
     training = None
     if not args.no_train:
-        training = train_bench(dev)
+        training = {"fp32": train_bench(dev), "bf16_conv": train_bench(dev, precision="bf16")}
         log(f"bench: training step {training}")
+
+    bbh_batches = d0 = None
+    if not args.no_extra:
+        bbh_batches = bbhnet_batch_bench(dev)
+        log(f"bench: bbhnet batches {bbh_batches}")
+        d0 = d0_latency(dev)
+        log(f"bench: deepclean 1-s window fp32 latency {d0}")
 
     serving = None
     if not args.no_serve:
@@ -562,8 +650,10 @@ def main():
                                "77 BBHnet streams (2 ch x 2048, 2048 Hz), strides 1/16-1/4 s",
                    "streams": N_DC + N_BB, "samples_per_step": step_samples,
                    "channel_samples_per_step": int(DC_C * dc_s.sum() + BB_C * bb_s.sum())},
+        "channel_samples_per_s": value * (DC_C * dc_s.sum() + BB_C * bb_s.sum()) / step_samples,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
+        "bbhnet_batches": bbh_batches, "deepclean_1s_fp32": d0,
         "fp32_plain": plain, "causal_band": band, "serving": serving, "training": training, "roofline": roof,
         "cpu_baseline": cpu,
     }
