@@ -340,10 +340,26 @@ __device__ __forceinline__ void store_shortcut(uint16_t* xt, const ShortRaw<CSP,
 // CSP > 0 (residual stage) the 1x1 stride-2 shortcut of the stage input is
 // added to the same accumulators as extra K steps.
 // ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Request K step `ks` of this block's weight fragments (piece e = fragment
+// e >> 6, lane e & 63) into registers; steps past the end are skipped.
+template <int MT, int MTB, int KS, int ACH, int APT>
+__device__ __forceinline__ void fetch_kstep(u32x4 (&dst)[APT], const u32x4* wp, int ms, int ks) {
+#pragma unroll
+  for (int k = 0; k < APT; ++k) {
+    const int e = threadIdx.x + 256 * k, f = e >> 6, mt = f % MTB, ph = f / MTB;
+    if (e < ACH && ks < KS) dst[k] = wp[((ph * MT + ms * MTB + mt) * KS + ks) * 64 + (e & 63)];
+  }
+}
+
 template <int CIP, int MT, int NPH, int KT, int SC, int NTW, int EPI, int IN, bool OUT_F32, bool XS_F32,
-          int CSP, int MS>
+          int CSP, int MS, int AM>
 __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   static_assert(MT % MS == 0, "the m-split divides the output-channel tiles");
+  // AM = 1 (large batches): the block's weight fragments pass through LDS one
+  // K step at a time, double-buffered, fetched from L2 while the previous
+  // step computes; all four waves share them.
   constexpr int MTB = MT / MS;  // output-channel tiles of this block
   constexpr int TN = 64 * NTW;
   constexpr int ROWS = SC * (TN - 1) + KT;
@@ -358,10 +374,13 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * TNO ? (ROWS + 1) * RS : 16 * MTB * TNO;
   // weights staged in LDS once per block when they fit beside the tile; only
   // then is the next tile prefetched (LDS reads do not wait on global loads)
-  constexpr bool ALDS = 2 * TILE + NFRAG * 1024 <= 80 * 1024;
+  constexpr bool ALDS = AM == 0 && 2 * TILE + NFRAG * 1024 <= 80 * 1024;
+  constexpr int ACH = AM ? NPH * MTB * 64 : 1;  // 16-byte pieces of one K step's fragments
+  constexpr int APT = (ACH + 255) / 256;        // pieces per thread
   __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
   __shared__ __attribute__((aligned(16))) uint16_t xt[CSP > 0 ? (TN + 1) * RSX : 8];
   __shared__ __attribute__((aligned(16))) uint4 alds[ALDS ? NFRAG * 64 : 1];
+  __shared__ __attribute__((aligned(16))) uint4 achunk[2 * ACH];
   __shared__ float cst[2][16 * MTB];
   __shared__ float wsum[4];
 
@@ -410,6 +429,14 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
     const int col0 = (t % tiles_per) * TN;
     store_input<CIP, ROWS, RS, IN>(tile, raw, SC * col0 - padc);
     if (CSP > 0) store_shortcut<CSP, TN, RSX>(xt, sraw);
+    if constexpr (AM == 1) {
+      // K step 0's fragments into buffer 0 (piece e = fragment (e >> 6), lane e & 63)
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        const int e = threadIdx.x + 256 * k, f = e >> 6, mt = f % MTB, ph = f / MTB;
+        if (e < ACH) achunk[e] = wp[((ph * MT + ms * MTB + mt) * KS + 0) * 64 + (e & 63)];
+      }
+    }
     __syncthreads();
     if (ALDS) {
       const int tn = t + tstep;
@@ -427,11 +454,62 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
 #pragma unroll
         for (int mt = 0; mt < MTB; ++mt) acc[nt][ph][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    if constexpr (AM == 1) {
+      // register ring of AD stages: the fragments of step ks + AD - 1 are
+      // requested while step ks computes, so an L2 round trip has AD - 1
+      // steps to complete; one LDS buffer pair holds steps ks and ks + 1
+      constexpr int AD = 4;
+      const u32x4* wv = reinterpret_cast<const u32x4*>(p.wpk);
+      u32x4 an0[APT], an1[APT], an2[APT], an3[APT];
+      u32x4(*an[AD])[APT] = {&an0, &an1, &an2, &an3};
+      static_assert(AD == 4, "four named ring slots");
+      fetch_kstep<MT, MTB, KS, ACH, APT>(an1, wv, ms, 1);  // steps 1 .. 3 (step 0 is in LDS)
+      fetch_kstep<MT, MTB, KS, ACH, APT>(an2, wv, ms, 2);
+      fetch_kstep<MT, MTB, KS, ACH, APT>(an3, wv, ms, 3);
+#pragma unroll 1
+      for (int k0 = 0; k0 < KS; k0 += AD) {
+#pragma unroll
+        for (int d = 0; d < AD; ++d) {
+          const int ks = k0 + d;
+          if (ks >= KS) break;  // block-uniform
+          const uint4* ab = achunk + (ks & 1) * ACH;
+          const int kappa = 32 * ks + 8 * lg;
+          const int jj = kappa / CIP, i0 = kappa - jj * CIP;
+          uint4 af[NPH][MTB];
+#pragma unroll
+          for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+            for (int mt = 0; mt < MTB; ++mt) af[ph][mt] = ab[(ph * MTB + mt) * 64 + lane];
+#pragma unroll
+          for (int nt = 0; nt < NTW; ++nt) {
+            const int c = (wave * NTW + nt) * 16 + lc;
+            const int row = (jj < KT) ? SC * c + jj : ROWS;
+            const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&tile[row * RS + i0]));
+#pragma unroll
+            for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+              for (int mt = 0; mt < MTB; ++mt)
+                acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[ph][mt]),
+                                                                         bb, acc[nt][ph][mt], 0, 0, 0);
+          }
+          // step ks + 1 (requested AD - 1 steps ago, ring slot (d + 1) mod AD)
+          // to the other LDS buffer; then request step ks + AD into the freed slot
+          if (ks + 1 < KS) {
+            u32x4* dst = reinterpret_cast<u32x4*>(achunk + ((ks + 1) & 1) * ACH);
+#pragma unroll
+            for (int k = 0; k < APT; ++k)
+              if (threadIdx.x + 256 * k < ACH) dst[threadIdx.x + 256 * k] = (*an[(d + 1) % AD])[k];
+          }
+          fetch_kstep<MT, MTB, KS, ACH, APT>(*an[d], wv, ms, ks + AD);
+          __syncthreads();  // step ks + 1 staged; buffer ks & 1 free for step ks + 2
+        }
+      }
+    }
     // few accumulators: unroll so the next K steps' LDS reads are in flight
     // during this step's MFMAs; many accumulators: keep the loop rolled
     constexpr int KUNROLL = NTW * NPH * MTB <= 2 ? 4 : 1;
 #pragma unroll KUNROLL
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int ks = 0; ks < (AM == 1 ? 0 : KS); ++ks) {
       const int kappa = 32 * ks + 8 * lg;
       const int jj = kappa / CIP, i0 = kappa - jj * CIP;
       uint4 af[NPH][MTB];
@@ -571,18 +649,18 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
 // Dispatch over the instantiated shapes.
 // ---------------------------------------------------------------------------
 struct Key {
-  int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32, csp;
+  int cip, mt, nph, kt, sc, epi, in, out_f32, xs_f32, csp, am;
 };
 
 template <int CIP, int MT, int NPH, int KT, int SC, int EPI, int IN, bool OUT_F32, bool XS_F32, int CSP, int NTW,
-          int MS>
+          int MS, int AM>
 static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   constexpr int TN = 64 * NTW, MTB = MT / MS;
   // same test as the kernel's ALDS: persistent grid only when weights fit in LDS
   constexpr int ROWS = SC * (TN - 1) + KT, RS = CIP + 8, KS = (KT * CIP + 31) / 32;
   constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * NPH * TN ? (ROWS + 1) * RS : 16 * MTB * NPH * TN;
-  constexpr bool ALDS = 2 * TILE + NPH * MTB * KS * 1024 <= 80 * 1024;
-  auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP, MS>;
+  constexpr bool ALDS = AM == 0 && 2 * TILE + NPH * MTB * KS * 1024 <= 80 * 1024;
+  auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP, MS, AM>;
   const int64_t tiles = (int64_t)((g.ncol + TN - 1) / TN) * p.n;
   if (tiles * MS > (int64_t)1 << 30) return hipErrorInvalidValue;
   if (!ALDS) {
@@ -605,53 +683,69 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32, CSP, NTW, MS) of every
+// (CIP, MT, NPH, KT, SC, EPI, IN, OUT_F32, XS_F32, CSP, NTW, MS, AM) of every
 // compiled variant: NTW 16-column tiles per wave (a block covers 64 NTW
-// columns) and an m-split MS (a block computes MT / MS output-channel tiles).
+// columns), an m-split MS (a block computes MT / MS output-channel tiles) and
+// the weight path AM (0: resident in LDS or read per wave; 1: staged per K
+// step, for large batches).
 // The BBHnet layers are small GEMMs whose weights outweigh a window's
 // activations: each block keeps one output-channel tile's weights in LDS and
 // streams narrow column tiles past them.
 #define GW_BF16_VARIANTS(X)                                                         \
   /* DeepClean-shaped encoder (k7 s2), first layer from FP32 or ring */            \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1)                \
-  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1)               \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1)                 \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1)                \
-  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)                \
-  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
-  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1, 0)           \
+  X(24, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1, 0)          \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_F32, false, false, 0, 4, 1, 0)            \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_RING, false, false, 0, 4, 1, 0)           \
+  X(8, 1, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)           \
+  X(16, 2, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)          \
+  X(32, 4, 1, 7, 2, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)          \
   /* decoder (transposed k7 s2 p3 op1: 2 phases of 4 taps) */                      \
-  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
-  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
-  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)               \
-  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1)                \
+  X(64, 2, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)          \
+  X(32, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)          \
+  X(16, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)          \
+  X(8, 1, 2, 4, 1, EPI_AFFINE_TANH, IN_BF16, false, false, 0, 4, 1, 0)           \
   /* output conv k7 s1 with causal slice + subtraction */                          \
-  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false, 0, 4, 1)                         \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_BF16, true, false, 0, 4, 1, 0)                    \
   /* BBHnet-shaped stages: conv_a, then conv_b + 1x1 stride-2 shortcut */           \
-  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0, 1, 2)                        \
-  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8, 1, 2)                 \
-  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 4)                      \
-  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32, 1, 4)               \
-  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 8)                      \
-  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64, 1, 8)               \
-  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64, 1, 8)                \
+  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0, 1, 2, 0)                   \
+  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8, 1, 2, 0)            \
+  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 4, 0)                 \
+  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32, 1, 4, 0)          \
+  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 1, 8, 0)                 \
+  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64, 1, 8, 0)          \
+  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64, 1, 8, 0)           \
+  /* BBHnet layers at large batches: all output channels per block, weights   \
+     staged per K step */                                                      \
+  X(8, 2, 1, 7, 2, EPI_RELU, IN_F32, false, false, 0, 4, 1, 1)                 \
+  X(32, 2, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, true, 8, 4, 1, 1)          \
+  X(32, 4, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 2, 1, 1)               \
+  X(64, 4, 1, 7, 1, EPI_RESID_RELU, IN_BF16, false, false, 32, 2, 1, 1)        \
+  X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 2, 2, 1)               \
+  X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64, 2, 1, 1)        \
+  X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64, 2, 1, 1)         \
   /* training forward (BF16 conv variant): FP32 activations in, FP32 z out */      \
-  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                         \
-  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                        \
-  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1)                         \
-  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1)                          \
-  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1)
+  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                    \
+  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
+  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                    \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                     \
+  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                    
 
-int conv_bf16_gap_parts(int Co, int Lout) {
+// Large batches (at least ~4 blocks of 128 columns per CU) take the AM = 1
+// variants where they exist.
+static bool large_batch(int n, int ncol) { return (int64_t)n * ncol >= 256 * 128 * 4; }
+
+int conv_bf16_gap_parts(int Co, int Lout, int n) {
   // partial sums per window written by the pooled (EPI_RESID_GAP) variant
   const int mt = (Co + 15) / 16;
-#define GW_GAP(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS) \
-  if (EPI == EPI_RESID_GAP && mt == MT) return (Lout + 64 * NTW - 1) / (64 * NTW) * MS;
+  const int am = large_batch(n, Lout) ? 1 : 0;
+#define GW_GAP(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM) \
+  if (EPI == EPI_RESID_GAP && mt == MT && AM == am) return (Lout + 64 * NTW - 1) / (64 * NTW) * MS;
   GW_BF16_VARIANTS(GW_GAP)
 #undef GW_GAP
   return -1;
@@ -663,7 +757,7 @@ bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
   if (tr && stride != 2) return false;
   const Geo g = make_geo(tr, k, stride, 3, 1 << 20);
   const int cip = cip_of(Ci), mt = (Co + 15) / 16;
-#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS) \
+#define GW_SHAPE(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM) \
   if (cip == CIP && mt == MT && g.nph == NPH && g.kt == KT && g.sc == SC) return true;
   GW_BF16_VARIANTS(GW_SHAPE)
 #undef GW_SHAPE
@@ -691,10 +785,14 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
   k.csp = res ? cip_of(p.Cs) : 0;
   if (res && (!p.wspk || p.Ls != 2 * p.Lout)) return hipErrorInvalidValue;
   if (epi == EPI_RESID_GAP && (!p.hw || !p.gap_part)) return hipErrorInvalidValue;
-#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS)                            \
+#define GW_LAUNCH(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM)                        \
   if (k.cip == CIP && k.mt == MT && k.nph == NPH && k.kt == KT && k.sc == SC && k.epi == EPI && \
-      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF && k.csp == CS)                 \
-    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS>(p, g, st);
+      k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF && k.csp == CS && k.am == AM)   \
+    return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM>(p, g, st);
+  // the large-batch variant when one exists, else the general one
+  k.am = large_batch(p.n, g.ncol) ? 1 : 0;
+  GW_BF16_VARIANTS(GW_LAUNCH)
+  k.am = 0;
   GW_BF16_VARIANTS(GW_LAUNCH)
 #undef GW_LAUNCH
   return hipErrorNotSupported;

@@ -88,3 +88,14 @@ def test_bbhnet_bf16_batch_independent(bb):
     full = m.forward(x=xt, precision=gs.BF16)
     part = m.forward(x=xt[7:19].contiguous(), precision=gs.BF16)
     assert torch.equal(full[7:19], part)
+
+
+def test_bbhnet_bf16_batch_independent_large(bb):
+    """Large batches use the weight-staging variants (every layer of both
+    calls below); a window's logit does not depend on the rest of the batch."""
+    m, _ = bb
+    x, _ = synth.bbh_windows(78, 1024)
+    xt = torch.from_numpy(x).to(DEV)
+    full = m.forward(x=xt, precision=gs.BF16)
+    part = m.forward(x=xt[256:768].contiguous(), precision=gs.BF16)
+    assert torch.equal(full[256:768], part)
