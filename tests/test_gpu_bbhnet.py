@@ -99,3 +99,16 @@ def test_bbhnet_bf16_batch_independent_large(bb):
     full = m.forward(x=xt, precision=gs.BF16)
     part = m.forward(x=xt[256:768].contiguous(), precision=gs.BF16)
     assert torch.equal(full[256:768], part)
+
+
+def test_bbhnet_bf16_large_batch_ragged_window(bb):
+    """Large-batch variants on a window whose layer lengths are not multiples
+    of their 128/256-column tiles (2576 -> 1288 -> 644 -> 322): sampled
+    windows against the oracle."""
+    m, params = bb
+    B, W = 1024, 2576
+    x = synth.gaussian(79, (B, 2, W))
+    got = m.forward(x=torch.from_numpy(x).to(DEV), precision=gs.BF16).cpu().numpy()
+    assert np.isfinite(got).all()
+    idx = np.sort(np.random.default_rng(80).choice(B, size=24, replace=False))
+    assert rel(got[idx], ref.bbhnet_forward(params, x[idx])) <= 2e-2
