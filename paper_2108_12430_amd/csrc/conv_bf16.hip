@@ -889,7 +889,13 @@ constexpr int mn(int a, int b) { return a < b ? a : b; }
 // column tiles share one epilogue pass (lanes 32..63 take the second tile)
 constexpr bool COMPACT(int l) { return l < 8 && MT(l) == 1 && cip(C[l + 1]) == 8; }
 // column tiles per work unit: enough that every layer is one round of units
-constexpr int NTC(int l) { return COMPACT(l) ? mn(4, 2 * cdiv(NT(l), 2 * NW)) : mn(4, cdiv(NT(l), NW)); }
+// (times GW_FUSED_NTCMUL, at most 4)
+#ifndef GW_FUSED_NTCMUL
+#define GW_FUSED_NTCMUL 1
+#endif
+constexpr int NTC(int l) {
+  return COMPACT(l) ? mn(4, 2 * cdiv(NT(l), 2 * NW) * GW_FUSED_NTCMUL) : mn(4, cdiv(NT(l), NW) * GW_FUSED_NTCMUL);
+}
 constexpr int NG(int l) { return cdiv(NT(l), NTC(l)); }
 // per-layer table of B-fragment row offsets: KOFF[l][lg][ks] (elements) for
 // the 8 channels at kappa = 32 ks + 8 lg, i.e. tap jj = kappa / C_in and
@@ -904,7 +910,7 @@ __host__ __device__ constexpr int koff(int l, int lg, int ks) {
 // the (phase, channel tile) pairs of a layer with few column groups are
 // split over SPL waves
 #ifndef GW_FUSED_MAXSPL
-#define GW_FUSED_MAXSPL 4
+#define GW_FUSED_MAXSPL 2
 #endif
 constexpr int SPL(int l) {
   return COMPACT(l) ? 1
