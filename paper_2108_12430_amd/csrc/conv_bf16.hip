@@ -824,7 +824,7 @@ namespace fused {
 constexpr int T = GW_FUSED_T;  // output samples per block (a multiple of 256)
 static_assert(T % 256 == 0, "tile must hold whole 16-column MFMA tiles at every layer");
 #ifndef GW_FUSED_WAVES
-#define GW_FUSED_WAVES 16
+#define GW_FUSED_WAVES 12
 #endif
 constexpr int NW = GW_FUSED_WAVES;  // waves per block
 constexpr int NTHR = 64 * NW;
@@ -860,9 +860,6 @@ constexpr int MT(int l) { return (C[l + 1] + 15) / 16; }
 constexpr int NPH(int l) { return l >= 4 && l < 8 ? 2 : 1; }
 constexpr int KS(int l) { return (KT(l) * cip(C[l]) + 31) / 32; }
 constexpr int NFRAG(int l) { return NPH(l) * MT(l) * KS(l); }
-// all nine layers' weight fragments stay in LDS: layer l's start (in fragments)
-constexpr int WOFF(int l) { return l == 0 ? 0 : WOFF(l - 1) + NFRAG(l - 1); }
-constexpr int WTOT = WOFF(9);
 
 }  // namespace fused
 
@@ -1032,10 +1029,12 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
 
 // One layer of the fused network: LDS in -> LDS out (or global for the last).
 // Work units are (group of NTC column tiles, share of the (phase, channel
-// tile) pairs); unit u goes to wave u mod NW.  kt holds the layer's row of
-// the B-offset table.
+// tile) pairs); unit u goes to wave u mod NW.  A unit requests all of its
+// weight fragments (at most 16, 64 VGPRs) from global memory before its first
+// MFMA; the 92 KB of packed weights stay in L2, shared by every block.  kt
+// holds the layer's row of the B-offset table.
 template <int l>
-__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wl,
+__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
                                             const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
                                             const ConvP* op, int b, int Wout) {
   using namespace fused;
@@ -1059,7 +1058,13 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
   for (int unit = wave; unit < NG(l) * SP; unit += NW) {
     const int nt0 = (unit / SP) * NTCl, sp = unit % SP;  // wave-uniform
     const uint16_t* colbase = in + ((nt0 * 16 + lc) * SX) * RSI;
-    const uint4* wq = wl + sp * KSn * 64 + lane;
+    // fragment (pair q = sp + k SP = ph * M + mt, K step ks) of this lane
+    const u32x4* wq = reinterpret_cast<const u32x4*>(wg) + sp * KSn * 64 + lane;
+    u32x4 af[Q][KSn];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int ks = 0; ks < KSn; ++ks) af[k][ks] = wq[(k * SP * KSn + ks) * 64];
     f32x4 acc[NTCl][Q];
 #pragma unroll
     for (int a = 0; a < NTCl; ++a)
@@ -1067,9 +1072,6 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
       for (int k = 0; k < Q; ++k) acc[a][k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KSn; ++ks) {
-      uint4 af[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) af[k] = wq[(k * SP * KSn + ks) * 64];  // pair q = sp + k SP = ph * M + mt
       const uint16_t* src = colbase + ko[ks];
 #pragma unroll
       for (int a = 0; a < NTCl; ++a) {
@@ -1077,7 +1079,7 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
         const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + a * 16 * SX * RSI));
 #pragma unroll
         for (int k = 0; k < Q; ++k)
-          acc[a][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[k]), bb, acc[a][k], 0, 0, 0);
+          acc[a][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[k][ks]), bb, acc[a][k], 0, 0, 0);
       }
     }
     if (edge)
@@ -1243,14 +1245,13 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
 }
 
 #ifndef GW_FUSED_WAVES_PER_SIMD
-#define GW_FUSED_WAVES_PER_SIMD 1
+#define GW_FUSED_WAVES_PER_SIMD 6
 #endif
 template <int IN>
 __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused(ConvP p, FusedP f, int ntile) {
   using namespace fused;
   __shared__ __attribute__((aligned(16))) uint16_t bufA[BUFA];
   __shared__ __attribute__((aligned(16))) uint16_t bufB[BUFB];
-  __shared__ __attribute__((aligned(16))) uint4 wl[WTOT * 64];
   __shared__ __attribute__((aligned(16))) int ktab[9][4][KSMAX];
   __shared__ __attribute__((aligned(16))) float ksc[9][64];
   __shared__ __attribute__((aligned(16))) float ksh[9][64];
@@ -1265,8 +1266,6 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
   load_x<IN>(raw, p, t0 / tpw, (t0 % tpw) * T + LO[0]);
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
-    const uint4* src = reinterpret_cast<const uint4*>(f.wpk[l]);
-    for (int e = threadIdx.x; e < NFRAG(l) * 64; e += NTHR) wl[WOFF(l) * 64 + e] = src[e];
     if (threadIdx.x < 64) {
       const int oc = (int)threadIdx.x < C[l + 1] ? (int)threadIdx.x : C[l + 1] - 1;
       const float g = l < 8 ? kTwoLog2e : 1.0f;  // tanh layers take z = 2 x log2(e)
@@ -1285,10 +1284,6 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
   for (int t = t0; t < t1; ++t) {
     const int b = t / tpw, u0 = (t % tpw) * T;
     const bool more = t + 1 < t1;  // block-uniform
-    const int nb = (t + 1) / tpw, nq = ((t + 1) % tpw) * T + LO[0];
-    // FP32 input takes twice the registers: it is loaded after the last layer
-    constexpr bool PREFETCH = IN != IN_F32;
-    if (PREFETCH && more) load_x<IN>(raw, p, nb, nq);
 
     // layer l reads the buffer holding a_l and writes a_{l+1}; u0 scaled per
     // layer; an opaque copy of the thread index keeps each layer's address
@@ -1297,8 +1292,8 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     {                                                                                                       \
       int tid = threadIdx.x;                                                                                \
       asm volatile("" : "+v"(tid));                                                                         \
-      fused_layer<l>(tid, IN_BUF, OUT_BUF, wl + WOFF(l) * 64, &ktab[l][0][0], ksc[l], ksh[l],              \
-                     u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);                              \
+      fused_layer<l>(tid, IN_BUF, OUT_BUF, reinterpret_cast<const uint4*>(f.wpk[l]), &ktab[l][0][0],       \
+                     ksc[l], ksh[l], u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);             \
       __syncthreads();                                                                                      \
     }
     GW_FUSED_LAYER(0, bufA, bufB, 2)
@@ -1312,7 +1307,9 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     GW_FUSED_LAYER(8, bufA, bufB, 1)
 #undef GW_FUSED_LAYER
     if (more) {
-      if (!PREFETCH) load_x<IN>(raw, p, nb, nq);
+      // the next tile's input: the other block on the CU hides its latency
+      const int nq = ((t + 1) % tpw) * T + LO[0];
+      load_x<IN>(raw, p, (t + 1) / tpw, nq);
       store_x<IN>(bufA, raw, nq);
       __syncthreads();
     }
