@@ -1371,7 +1371,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       int epi_b = gw::EPI_RESID_RELU;
       if (last) {
         // last stage: the pooling head is fused into the epilogue
-        const int nblk = gw::conv_bf16_gap_parts(sd.co, Lo, n);
+        const int nblk = gw::conv_bf16_gap_parts(pb.Ci, sd.co, Lo, n);
         if (nblk < 1 || nblk > kGapParts) return fail(GW_EUNSUPPORTED, "window too long for the fused pooling head");
         pb.hw = P + m->head_w;
         pb.gap_part = reinterpret_cast<float*>(wsb + b.gap);
@@ -1382,7 +1382,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       LAUNCH(nm("bbh_conva_bf16", "S", s), st, gw::launch_conv_bf16(pa, false, gw::EPI_RELU, gw::SRC_DENSE, st));
       LAUNCH(nm("bbh_convb_bf16", "S", s), st, gw::launch_conv_bf16(pb, false, epi_b, gw::SRC_DENSE, st));
       if (last) {
-        const int nblk = gw::conv_bf16_gap_parts(sd.co, Lo, n);
+        const int nblk = gw::conv_bf16_gap_parts(pb.Ci, sd.co, Lo, n);
         LAUNCH("gap_finalize", st,
                gw::launch_gap_finalize(pb.gap_part, nblk, P + m->head_b, logits, n, Lo, st));
       }

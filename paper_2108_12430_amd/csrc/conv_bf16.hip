@@ -736,14 +736,21 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                     \
   X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                    
 
-// Large batches (at least ~4 blocks of 128 columns per CU) take the AM = 1
-// variants where they exist.
-static bool large_batch(int n, int ncol) { return (int64_t)n * ncol >= 256 * 128 * 4; }
+// Large layers take the AM = 1 variants where they exist: at least ~4 blocks
+// of 128 columns per CU, or, for layers with C_in x C_out >= 4096, at least
+// 1.5M output values (columns x C_out).  An AM = 1 block runs the whole K loop
+// with a barrier per K step, a floor of ~15-25 us on the BBHnet stages; the
+// small-batch kernels grow with the batch and cross that floor near this
+// size (measured per layer at 8-256 windows).
+static bool large_batch(int n, int ncol, int Ci, int Co) {
+  const int64_t cols = (int64_t)n * ncol;
+  return cols >= 256 * 128 * 4 || (cols * Co >= 1536 * 1024 && Ci * Co >= 4096);
+}
 
-int conv_bf16_gap_parts(int Co, int Lout, int n) {
+int conv_bf16_gap_parts(int Ci, int Co, int Lout, int n) {
   // partial sums per window written by the pooled (EPI_RESID_GAP) variant
   const int mt = (Co + 15) / 16;
-  const int am = large_batch(n, Lout) ? 1 : 0;
+  const int am = large_batch(n, Lout, Ci, Co) ? 1 : 0;
 #define GW_GAP(CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM) \
   if (EPI == EPI_RESID_GAP && mt == MT && AM == am) return (Lout + 64 * NTW - 1) / (64 * NTW) * MS;
   GW_BF16_VARIANTS(GW_GAP)
@@ -790,7 +797,7 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
       k.in == IN && k.out_f32 == (int)OF && k.xs_f32 == (int)XF && k.csp == CS && k.am == AM)   \
     return launch_t<CIP, MT, NPH, KT, SC, EPI, IN, OF, XF, CS, NTW, MS, AM>(p, g, st);
   // the large-batch variant when one exists, else the general one
-  k.am = large_batch(p.n, g.ncol) ? 1 : 0;
+  k.am = large_batch(p.n, g.ncol, p.Ci, p.Co) ? 1 : 0;
   GW_BF16_VARIANTS(GW_LAUNCH)
   k.am = 0;
   GW_BF16_VARIANTS(GW_LAUNCH)

@@ -75,7 +75,7 @@ struct ConvP {
 hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool transposed);
-int conv_bf16_gap_parts(int Co, int Lout, int n);  // GAP partial sums per window (EPI_RESID_GAP), -1 if none
+int conv_bf16_gap_parts(int Ci, int Co, int Lout, int n);  // GAP partial sums per window (EPI_RESID_GAP), -1 if none
 // Fused DeepClean network (21->8->16->32->64 convs, 64->32->16->8->8
 // transposed convs, 8->1 output conv, all k7 p3; BN+tanh on all but the last)
 bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,

@@ -70,9 +70,12 @@ def test_bbhnet_from_pool_bitwise(bb):
     assert rel(got, ref.bbhnet_forward(params, dense)) <= 1e-5
 
 
-@pytest.mark.parametrize("B", [64, 256, 1024])
+@pytest.mark.parametrize("B", [8, 64, 256, 1024])
 def test_bbhnet_bf16(bb, B):
-    """BF16 MFMA convolutions with FP32 accumulation, epilogue and logits."""
+    """BF16 MFMA convolutions with FP32 accumulation, epilogue and logits.
+    8 windows take the small-batch kernels in every layer, 64 and 256 a mix
+    (the wide layers switch to the weight-staging kernels first), 1024 the
+    weight-staging kernels in every layer."""
     m, params = bb
     x, _ = synth.bbh_windows(3 + B, B)
     got = m.forward(x=torch.from_numpy(x).to(DEV), precision=gs.BF16).cpu().numpy()
@@ -82,12 +85,28 @@ def test_bbhnet_bf16(bb, B):
 
 
 def test_bbhnet_bf16_batch_independent(bb):
+    """24 and 12 windows take the same (small-batch) kernel in every layer:
+    a window's logit does not depend on the rest of the batch."""
     m, _ = bb
-    x, _ = synth.bbh_windows(77, 40)
+    x, _ = synth.bbh_windows(77, 24)
     xt = torch.from_numpy(x).to(DEV)
     full = m.forward(x=xt, precision=gs.BF16)
     part = m.forward(x=xt[7:19].contiguous(), precision=gs.BF16)
     assert torch.equal(full[7:19], part)
+
+
+def test_bbhnet_bf16_across_kernel_modes(bb):
+    """64 windows run the wide layers of stages 1 and 2 on the weight-staging
+    kernels, 12 windows every layer on the small-batch kernels: the same
+    windows agree to well within the BF16 bound (only the summation order
+    differs)."""
+    m, params = bb
+    x, _ = synth.bbh_windows(81, 64)
+    xt = torch.from_numpy(x).to(DEV)
+    full = m.forward(x=xt, precision=gs.BF16).cpu().numpy()
+    part = m.forward(x=xt[20:32].contiguous(), precision=gs.BF16).cpu().numpy()
+    assert rel(full[20:32], part) <= 2e-3
+    assert rel(part, ref.bbhnet_forward(params, x[20:32])) <= 2e-2
 
 
 def test_bbhnet_bf16_batch_independent_large(bb):
