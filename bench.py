@@ -33,6 +33,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+N_CUS = 256  # MI355X compute units
 METRIC = "streamed samples/sec + p99 per-update latency, BF16 batched vs FP32 plain"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
@@ -395,6 +396,9 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
+    ap.add_argument("--dc-cus", type=int, default=224,
+                    help="CU budget of the fused DeepClean kernel (0: all CUs); the CUs left over run the "
+                         "BBHnet group's kernels concurrently")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -414,6 +418,7 @@ def main():
     stages = synth.bbhnet_stages()
     dc = gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(dev), layers)
     bb = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(dev), stages)
+    dc.set_cu_budget(args.dc_cus)
     prec = gs.BF16 if args.precision == "bf16" else gs.FP32
     try:
         dc.workspace_bytes(1, DC_W, prec)
@@ -475,9 +480,9 @@ def main():
     log(f"bench: staged {n_steps_total} steps of inputs in HBM")
 
     # the two model groups are independent after the ingest: BBHnet runs on a
-    # second HIP stream (default priority) and fills the CUs that the
-    # DeepClean grid leaves free; the main stream waits for it before the
-    # next ingest overwrites the rings
+    # second HIP stream (default priority) on the CUs that the DeepClean
+    # kernel's budget leaves free (and on any CU once DeepClean is done); the
+    # main stream waits for it before the next ingest overwrites the rings
     s_main, s_bb = torch.cuda.current_stream(), torch.cuda.Stream()
     ev_in, ev_bb = torch.cuda.Event(), torch.cuda.Event()
 
@@ -591,6 +596,9 @@ def main():
         roof["traffic"] = traffic_for(name)
         roof["kernel"] = name
         roof["avg_us"] = avg_s * 1e6
+        if name == "dc_fused_bf16":
+            # the step runs the fused kernel on its CU budget, beside BBHnet
+            roof["cus"] = min(args.dc_cus, N_CUS) if args.dc_cus > 0 else N_CUS
         roof["algorithmic_flops"] = flops
         roof["algorithmic_bytes"] = by
         step_ms = sum(v[1] for v in prof.values()) / 5
@@ -661,7 +669,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "closed-loop serving mix: 179 DeepClean streams (21 ch x 32768, 4096 Hz) + "
                                "77 BBHnet streams (2 ch x 2048, 2048 Hz), strides 1/16-1/4 s",
-                   "streams": N_DC + N_BB, "samples_per_step": step_samples,
+                   "streams": N_DC + N_BB, "samples_per_step": step_samples, "deepclean_cus": args.dc_cus,
                    "channel_samples_per_step": int(DC_C * dc_s.sum() + BB_C * bb_s.sum())},
         "channel_samples_per_s": value * (DC_C * dc_s.sum() + BB_C * bb_s.sum()) / step_samples,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

@@ -174,6 +174,15 @@ int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_len, const f
                     gw_model** out);
 int gw_model_refresh(gw_model* model, void* hip_stream);
 int gw_model_free(gw_model* model);
+/* Compute-unit budget of a model's persistent kernels (the fused DeepClean
+ * forward, which otherwise keeps every CU busy for its whole run): their grid
+ * is sized for min(ncu, CUs of the device) CUs, so kernels of another model
+ * group on a second HIP stream find CUs free while it runs.  0 (the default)
+ * means every CU.  Outputs do not depend on the budget.  The setting is read
+ * at each launch; changing it while a forward of this model is being enqueued
+ * on another host thread races.  Errors: GW_EINVAL for a null model or
+ * ncu < 0. */
+int gw_model_set_cu_budget(gw_model* model, int32_t ncu);
 /* Number of float32 parameters a description implies. */
 int gw_model_n_params(int32_t kind, const int32_t* desc, int32_t desc_len, int64_t* n_params);
 

@@ -408,6 +408,7 @@ struct gw_model {
   Stager stager;
   bool bf16_all = false;
   bool fused = false;  // reference DeepClean shape: whole-network BF16 kernel available
+  int cu_budget = 0;   // CUs the persistent kernels size their grid for (0: all)
 };
 
 namespace {
@@ -683,6 +684,13 @@ extern "C" int gw_model_refresh(gw_model* m, void* hip_stream) {
   return pack_model(m, S(hip_stream));
 }
 
+extern "C" int gw_model_set_cu_budget(gw_model* m, int32_t ncu) {
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (ncu < 0) return fail(GW_EINVAL, "negative CU budget");
+  m->cu_budget = ncu;
+  return GW_OK;
+}
+
 extern "C" int gw_model_free(gw_model* m) {
   if (!m) return fail(GW_EINVAL, "null model");
   m->stager.release();
@@ -917,7 +925,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       sc[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].scale);
       sh[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].shift);
     }
-    LAUNCH("dc_fused_bf16", st, gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, st));
+    LAUNCH("dc_fused_bf16", st, gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, m->cu_budget, st));
     return GW_OK;
   }
   if (!(flags & GW_TRAIN)) {

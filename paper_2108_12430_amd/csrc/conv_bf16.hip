@@ -1339,7 +1339,7 @@ bool dc_fused_supported(const int* ci, const int* co, const int* type, const int
 // p: n, items (ring input or clean outputs), arena, x (+ ldx), noise, clean,
 // strain; W = window (or band) length, a multiple of 16.
 hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
-                                const float* const* shift, int W, bool ring, hipStream_t st) {
+                                const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st) {
   using namespace fused;
   if (W < 16 || W % 16) return hipErrorInvalidValue;
   FusedP f;
@@ -1376,7 +1376,8 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
     if (e != hipSuccess) return e;
     occ[v] = n > 0 ? n : 1;
   }
-  const int64_t grid = std::min<int64_t>(ntile, (int64_t)occ[v] * cus);
+  const int ncu = cu_budget > 0 && cu_budget < cus ? cu_budget : cus;
+  const int64_t grid = std::min<int64_t>(ntile, (int64_t)occ[v] * ncu);
   if (ring)
     hipLaunchKernelGGL(dc_fused<IN_RING>, dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
   else

@@ -26,7 +26,7 @@ _CODES = {1: "GW_EINVAL", 2: "GW_ENOMEM", 3: "GW_ESTATE", 4: "GW_EHIP", 5: "GW_E
 EXPORTS = [
     "gw_last_error", "gw_pool_init", "gw_pool_free", "gw_stream_open", "gw_stream_close",
     "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
-    "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_n_params",
+    "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
     "deepclean_workspace", "deepclean_forward", "deepclean_backward_scratch", "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "bbhnet_workspace", "bbhnet_forward",
     "gw_profile_begin", "gw_profile_end",
@@ -66,6 +66,7 @@ def lib():
             "gw_model_create": ([i32, vp, i32, vp, i64, vp, sz, vp, P(vp)], C.c_int),
             "gw_model_refresh": ([vp, vp], C.c_int),
             "gw_model_free": ([vp], C.c_int),
+            "gw_model_set_cu_budget": ([vp, i32], C.c_int),
             "gw_model_n_params": ([i32, vp, i32, P(i64)], C.c_int),
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
@@ -233,6 +234,11 @@ class _Model:
 
     def refresh(self, stream=None):
         check(lib().gw_model_refresh(self.h, _stream(stream)))
+
+    def set_cu_budget(self, ncu):
+        """Size the model's persistent kernels for at most ncu compute units
+        (0: all), leaving the rest to kernels on other streams."""
+        check(lib().gw_model_set_cu_budget(self.h, int(ncu)))
 
     def free(self):
         if getattr(self, "h", None) is not None:

@@ -71,6 +71,7 @@ def test_null_and_range_arguments_rejected():
     assert L.deepclean_forward(None, None, None, None, 1, 4096, None, None, None, None, 0, 0, None, 0,
                                None) == gs.GW_EINVAL
     assert L.bbhnet_forward(None, None, None, None, 1, 2048, None, 0, None, 0, None) == gs.GW_EINVAL
+    assert L.gw_model_set_cu_budget(None, 16) == gs.GW_EINVAL
     b = C.c_size_t()
     assert L.gw_bandpass_workspace(4, 32768, 4096.0, 70.0, 60.0, C.byref(b)) == gs.GW_EINVAL
     assert L.gw_bandpass_workspace(4, 32768, 4096.0, 55.0, 65.0, C.byref(b)) == gs.GW_OK

@@ -393,3 +393,25 @@ def test_fused_vs_layerwise_bf16(dc, W, n):
     m.forward(x=xt, noise=a2, precision=gs.BF16)
     torch.cuda.synchronize()
     assert torch.equal(a, a2)   # deterministic
+
+
+def test_cu_budget_bitwise(dc):
+    """A CU budget only resizes the fused kernel's persistent grid (fewer
+    blocks, more tiles each): outputs are bitwise those of the full grid.
+    Budgets: a few CUs, odd counts, and more CUs than the device has."""
+    m, _, _ = dc
+    n, W = 5, 32768
+    xt = torch.from_numpy(synth.gaussian(611, (n, 21, W))).to(DEV)
+    ref_out = torch.empty((n, W), device=DEV)
+    m.forward(x=xt, noise=ref_out, precision=gs.BF16)
+    try:
+        for ncu in (1, 7, 240, 100000):
+            m.set_cu_budget(ncu)
+            out = torch.empty((n, W), device=DEV)
+            m.forward(x=xt, noise=out, precision=gs.BF16)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref_out), ncu
+    finally:
+        m.set_cu_budget(0)
+    with pytest.raises(gs.GwError):
+        m.set_cu_budget(-1)
