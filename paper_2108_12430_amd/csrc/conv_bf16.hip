@@ -1050,7 +1050,9 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
   constexpr int NTCl = NTC(l), SP = SPL(l), Q = NPH(l) * MT(l) / SP;
   constexpr int SX = HALF(l) ? 1 : SC(l);  // LDS rows between adjacent columns
   static_assert(KSn <= KSMAX, "offset table width");
-  const int lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: in an SGPR, unit selection and the weight
+  // addresses are scalar work
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lc = lane & 15, lg = lane >> 4;
   // this lane's B row offsets for the layer's K steps
   int ko[KSMAX];
