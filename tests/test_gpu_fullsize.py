@@ -121,3 +121,37 @@ def test_bbhnet_bench_launch(mix):
     idx = sorted(mix["keep_bb"])
     exp = ref.bbhnet_forward(synth.bbhnet_params(0), np.stack([mix["keep_bb"][i] for i in idx]))
     assert rel(got[idx], exp) <= BF16_TOL
+
+
+def test_concurrent_streams_bitwise(mix):
+    """The benchmark's step: DeepClean (CU budget 224) on one HIP stream and
+    BBHnet on a second one, running at the same time, give bitwise the
+    outputs of the two forwards run one after the other on one stream."""
+    pool, dc_s, dcm, bbm = mix["pool"], mix["dc_s"], mix["dcm"], mix["bbm"]
+    ws_dc = torch.empty(dcm.workspace_bytes(N_DC, DC_W, gs.BF16), dtype=torch.uint8, device=DEV)
+    ws_bb = torch.empty(bbm.workspace_bytes(N_BB, BB_W, gs.BF16), dtype=torch.uint8, device=DEV)
+    clean_a = torch.empty(int(dc_s.sum()), device=DEV)
+    logits_a = torch.empty(N_BB, device=DEV)
+    dcm.forward(pool=pool, slots=mix["dc_slots"], W=DC_W, strides=dc_s, strain=mix["strain"], clean=clean_a,
+                precision=gs.BF16, ws=ws_dc)
+    bbm.forward(pool=pool, slots=mix["bb_slots"], W=BB_W, logits=logits_a, precision=gs.BF16, ws=ws_bb)
+    torch.cuda.synchronize()
+    s_main, s_bb = torch.cuda.current_stream(), torch.cuda.Stream()
+    ws_bb2 = torch.empty_like(ws_bb)
+    ev = torch.cuda.Event()
+    try:
+        dcm.set_cu_budget(224)
+        for _ in range(3):
+            clean_b = torch.full_like(clean_a, float("nan"))
+            logits_b = torch.full_like(logits_a, float("nan"))
+            ev.record(s_main)
+            s_bb.wait_event(ev)
+            dcm.forward(pool=pool, slots=mix["dc_slots"], W=DC_W, strides=dc_s, strain=mix["strain"],
+                        clean=clean_b, precision=gs.BF16, ws=ws_dc)
+            bbm.forward(pool=pool, slots=mix["bb_slots"], W=BB_W, logits=logits_b, precision=gs.BF16, ws=ws_bb2,
+                        stream=s_bb)
+            torch.cuda.synchronize()
+            assert torch.equal(clean_a, clean_b)
+            assert torch.equal(logits_a, logits_b)
+    finally:
+        dcm.set_cu_budget(0)
