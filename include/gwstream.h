@@ -209,10 +209,16 @@ int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t pre
  *          B.2 causal selection, App. B.4 subtraction); needs strides (host
  *          [n], 1 <= s_i <= W) and strain (device, same packing: the s_i
  *          newest strain samples of each item).
+ *   delays host [n] or NULL (all 0), with clean only: aggregation latency
+ *          d_i in [0, W - s_i] samples (App. B "Aggregation latency": the
+ *          prediction's noisy newest edge is dropped and the output waits
+ *          d_i samples).  Item i's clean block is then strain - noise[W - s_i
+ *          - d_i .. W - d_i), and its strain block holds the s_i strain
+ *          samples that end d_i samples before the window's newest sample.
  * precision GW_FP32 or GW_BF16.  flags: 0 (inference, running statistics),
  * GW_TRAIN (batch statistics over n*time per channel; requires x),
  * GW_TRAIN|GW_RECOMPUTE, or GW_CAUSAL (inference, clean output only; the
- * band is chosen from the largest stride and aligned to the network's total
+ * band is chosen from the largest s_i + d_i and aligned to the network's total
  * stride so every layer's sample grid coincides with the full window's).
  * Returns GW_EINVAL if ws_bytes is too small (the size deepclean_workspace
  * returns for the same n, W, precision and flags always suffices).
@@ -222,9 +228,9 @@ int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t pre
  * variants agree within the BF16 tolerance and each is bitwise reproducible.
  */
 int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, const float* x,
-                      int32_t n, int32_t W, const int32_t* strides, const float* strain, float* noise,
-                      float* clean, int32_t precision, uint32_t flags, void* ws, size_t ws_bytes,
-                      void* hip_stream);
+                      int32_t n, int32_t W, const int32_t* strides, const int32_t* delays,
+                      const float* strain, float* noise, float* clean, int32_t precision, uint32_t flags,
+                      void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
  * deepclean_backward (retraining): gradient of a scalar loss with respect to

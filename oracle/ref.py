@@ -268,6 +268,21 @@ def causal_clean(noise, strain_new):
     return tail, np.asarray(strain_new, np.float64) - tail
 
 
+def delayed_clean(noise, strain_seg, delay):
+    """Aggregation latency (App. B, "Aggregation latency"): the newest
+    `delay` predicted samples of each window are dropped as edge-degraded;
+    the output is the s samples before them, noise[W - s - delay : W - delay],
+    subtracted from the strain samples of the same span (the s strain samples
+    that end `delay` samples before the newest one).  delay = 0 is
+    causal_clean.  noise [B][W], strain_seg [B][s] -> (segment, clean)."""
+    noise = np.asarray(noise, np.float64)
+    s, W = strain_seg.shape[-1], noise.shape[-1]
+    if not 0 <= delay <= W - s:
+        raise ValueError("delay must be in [0, W - s]")
+    seg = noise[..., W - s - delay: W - delay]
+    return seg, np.asarray(strain_seg, np.float64) - seg
+
+
 # ---------------------------------------------------------------------------
 # BBHnet-shaped classifier
 # ---------------------------------------------------------------------------

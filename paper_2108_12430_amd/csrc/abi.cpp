@@ -822,8 +822,8 @@ extern "C" int deepclean_workspace(const gw_model* m, int32_t n, int32_t W, int3
 }
 
 extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x,
-                                 int32_t n, int32_t W, const int32_t* strides, const float* strain,
-                                 float* noise, float* clean, int32_t precision, uint32_t flags,
+                                 int32_t n, int32_t W, const int32_t* strides, const int32_t* delays,
+                                 const float* strain, float* noise, float* clean, int32_t precision, uint32_t flags,
                                  void* ws, size_t ws_bytes, void* hip_stream) {
   const hipStream_t st = S(hip_stream);
   if (!m) return fail(GW_EINVAL, "null model");
@@ -842,6 +842,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
 
   if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
   if (clean && (!strides || !strain)) return fail(GW_EINVAL, "clean output needs strides and strain");
+  if (delays && !clean) return fail(GW_EINVAL, "delays apply to the clean output");
   if (!ws) return fail(GW_EINVAL, "null workspace");
   {
     std::vector<int> l0, l1;
@@ -850,8 +851,15 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   // GW_CAUSAL: run the layers on the band [a, W) only
   int a_band = 0;
   if (flags & GW_CAUSAL) {
+    // the clean block of item i ends delay_i before W: the band must reach
+    // back s_i + delay_i samples (plus the receptive field)
     int smax = 1;
-    for (int i = 0; i < n; ++i) smax = std::max(smax, strides[i]);
+    for (int i = 0; i < n; ++i) {
+      if (strides[i] < 1 || strides[i] > W) return fail(GW_EINVAL, "stride must be in [1, W]");
+      const int d = delays ? delays[i] : 0;
+      if (d < 0 || d > W - strides[i]) return fail(GW_EINVAL, "delay must be in [0, W - stride]");
+      smax = std::max(smax, strides[i] + d);
+    }
     a_band = causal_band_start(m, W, smax);
   }
   const int Wb = W - a_band;
@@ -888,6 +896,8 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       if (clean) {
         if (strides[i] < 1 || strides[i] > W) return fail(GW_EINVAL, "stride must be in [1, W]");
         it.s = strides[i];
+        it.delay = delays ? delays[i] : 0;
+        if (it.delay < 0 || it.delay > W - it.s) return fail(GW_EINVAL, "delay must be in [0, W - stride]");
         it.out = off;
         off += strides[i];
       } else {

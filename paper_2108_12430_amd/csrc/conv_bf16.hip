@@ -594,8 +594,8 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
               if (p.noise) p.noise[(int64_t)b * W + u] = v[ph];
               if (p.clean) {
                 const Item& it = p.items[b];
-                const int t0 = W - it.s;
-                if (u >= t0) {
+                const int t0 = W - it.s - it.delay;
+                if (u >= t0 && u < t0 + it.s) {
                   const int64_t idx = it.out + (u - t0);
                   p.clean[idx] = p.strain[idx] - v[ph];
                 }
@@ -979,8 +979,8 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
       if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
       if (op->clean) {
         const Item& it = op->items[b];
-        const int t0 = Wout - it.s;
-        if (u >= t0) {
+        const int t0 = Wout - it.s - it.delay;
+        if (u >= t0 && u < t0 + it.s) {
           const int64_t idx = it.out + (u - t0);
           op->clean[idx] = op->strain[idx] - v;
         }

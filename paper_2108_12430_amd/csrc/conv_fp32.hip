@@ -48,8 +48,8 @@ __device__ __forceinline__ void store_out(const ConvP& p, int b, int o, int u, f
     if (p.noise) p.noise[(int64_t)b * W + u] = v;
     if (p.clean) {
       const Item& it = p.items[b];
-      const int t0 = W - it.s;
-      if (u >= t0) {
+      const int t0 = W - it.s - it.delay;
+      if (u >= t0 && u < t0 + it.s) {
         const int64_t idx = it.out + (u - t0);
         p.clean[idx] = p.strain[idx] - v;
       }

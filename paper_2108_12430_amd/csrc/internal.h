@@ -17,8 +17,10 @@ struct Item {
   int32_t head;    // ring index of the oldest sample (update: before writing)
   int32_t s;       // new samples per request (stride)
   int32_t C, W;
+  int32_t delay;   // forward: aggregation latency in samples (clean block ends delay before W)
+  int32_t pad_;
 };
-static_assert(sizeof(Item) == 48, "Item layout");
+static_assert(sizeof(Item) == 56, "Item layout");
 
 enum Epi : int {
   EPI_AFFINE = 0,       // y = acc*scale[o] + shift[o]

@@ -69,7 +69,7 @@ def lib():
             "gw_model_set_cu_budget": ([vp, i32], C.c_int),
             "gw_model_n_params": ([i32, vp, i32, P(i64)], C.c_int),
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
-            "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
+            "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
             "deepclean_backward_scratch": ([vp, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_backward": ([vp, i32, i32, vp, vp, vp, vp, u32, i32, vp, sz, vp], C.c_int),
             "gw_bandpass_workspace": ([i32, i32, f32, f32, f32, P(sz)], C.c_int),
@@ -273,7 +273,7 @@ class DeepClean(_Model):
         return b.value
 
     def forward(self, *, x=None, pool=None, slots=None, n=None, W=None, strides=None, strain=None,
-                noise=None, clean=None, precision=FP32, flags=0, ws=None, stream=None):
+                noise=None, clean=None, precision=FP32, flags=0, ws=None, stream=None, delays=None):
         """Enqueue deepclean_forward; outputs are caller-provided tensors (or
         None).  Returns the workspace used (holds the saved state for
         backward when flags has TRAIN)."""
@@ -290,7 +290,10 @@ class DeepClean(_Model):
             sl, psl = _host_i32(slots)
         if strides is not None:
             st, pst = _host_i32(strides)
-        check(lib().deepclean_forward(self.h, pool.h if pool is not None else None, psl, _ptr(x), n, W, pst,
+        dl = pdl = None
+        if delays is not None:
+            dl, pdl = _host_i32(delays)
+        check(lib().deepclean_forward(self.h, pool.h if pool is not None else None, psl, _ptr(x), n, W, pst, pdl,
                                       _ptr(strain), _ptr(noise), _ptr(clean), precision, flags, _ptr(ws),
                                       ws.numel(), _stream(stream)))
         return ws

@@ -68,7 +68,7 @@ def test_null_and_range_arguments_rejected():
     assert L.gw_pool_init(C.c_void_p(256), 1 << 20, 0, 4, C.byref(h)) == gs.GW_EINVAL
     assert L.gw_pool_init(C.c_void_p(257), 1 << 20, 4, 4, C.byref(h)) == gs.GW_EINVAL   # misaligned
     assert L.snapshot_update(None, 1, None, None, None, None, None) == gs.GW_EINVAL
-    assert L.deepclean_forward(None, None, None, None, 1, 4096, None, None, None, None, 0, 0, None, 0,
+    assert L.deepclean_forward(None, None, None, None, 1, 4096, None, None, None, None, None, 0, 0, None, 0,
                                None) == gs.GW_EINVAL
     assert L.bbhnet_forward(None, None, None, None, 1, 2048, None, 0, None, 0, None) == gs.GW_EINVAL
     assert L.gw_model_set_cu_budget(None, 16) == gs.GW_EINVAL

@@ -415,3 +415,64 @@ def test_cu_budget_bitwise(dc):
         m.set_cu_budget(0)
     with pytest.raises(gs.GwError):
         m.set_cu_budget(-1)
+
+
+@pytest.mark.parametrize("prec,flags,tol", [(gs.FP32, 0, FP32_TOL), (gs.BF16, 0, BF16_TOL),
+                                            (gs.BF16, gs.LAYERWISE, BF16_TOL)])
+def test_aggregation_delay(dc, prec, flags, tol):
+    """Aggregation latency: item i keeps noise[W - s_i - d_i, W - d_i) and
+    subtracts it from the strain of that span (delays 0, mid-window, the
+    oldest possible block, and a delay that is not a multiple of 16), for
+    both clean-output epilogues (fused BF16 kernel, per-layer kernels, FP32);
+    GW_CAUSAL with the same delays gives the same clean output bitwise."""
+    m, params, layers = dc
+    W = 4096
+    strides = [256, 512, 128, 1000]
+    delays = [0, 1536, W - 128, 37]
+    n = len(strides)
+    pool = gs.Pool(64 << 20, max_slots=8, max_items=8)
+    slots = [pool.open(21, W) for _ in range(n)]
+    data = [synth.witness_stream(700 + i, 6000) for i in range(n)]
+    fill = [4200, 4096, 5000, 4500]   # each >= W: the ring holds samples [fill - W, fill)
+    for i in range(n):
+        pool.update([slots[i]], [W], torch.from_numpy(np.ascontiguousarray(data[i][0][:, fill[i] - W:fill[i]]))
+                    .to(DEV).reshape(-1), [0])
+    # strain block of item i: the s_i samples ending d_i before the newest
+    strain = np.concatenate([data[i][1][fill[i] - strides[i] - delays[i]:fill[i] - delays[i]] for i in range(n)])
+    st_dev = torch.from_numpy(strain).to(DEV)
+    clean = torch.empty(sum(strides), device=DEV)
+    noise = torch.empty((n, W), device=DEV)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, delays=delays, strain=st_dev, clean=clean,
+              noise=noise, precision=prec, flags=flags)
+    torch.cuda.synchronize()
+    xs = np.stack([data[i][0][:, fill[i] - W:fill[i]] for i in range(n)])
+    en = ref.deepclean_forward(params, xs, layers)
+    assert rel(noise.cpu().numpy(), en) <= tol
+    got = clean.cpu().numpy()
+    o = 0
+    for i, s in enumerate(strides):
+        seg, ec = ref.delayed_clean(en[i:i + 1], strain[None, o:o + s], delays[i])
+        assert rel(got[o:o + s], ec[0]) <= tol, i
+        # the noise subtracted is the window's, at the delayed span
+        np.testing.assert_array_equal(got[o:o + s], strain[o:o + s] - noise.cpu().numpy()[i, W - s - delays[i]:
+                                                                                            W - delays[i]])
+        o += s
+    if flags == 0:
+        band = torch.empty_like(clean)
+        m.forward(pool=pool, slots=slots, W=W, strides=strides, delays=delays, strain=st_dev, clean=band,
+                  precision=prec, flags=gs.CAUSAL)
+        torch.cuda.synchronize()
+        assert torch.equal(clean, band)
+
+
+def test_aggregation_delay_rejected(dc):
+    m, _, _ = dc
+    W = 4096
+    x = torch.zeros((2, 21, W), device=DEV)
+    clean = torch.empty(512, device=DEV)
+    strain = torch.zeros(512, device=DEV)
+    for bad in ([0, -1], [0, W - 255]):
+        with pytest.raises(gs.GwError):
+            m.forward(x=x, strides=[256, 256], delays=bad, strain=strain, clean=clean, precision=gs.BF16)
+    with pytest.raises(gs.GwError):     # delays without a clean output
+        m.forward(x=x, noise=torch.empty((2, W), device=DEV), delays=[0, 0], precision=gs.BF16)

@@ -442,3 +442,46 @@ def test_receptive_field_band(s):
         a2 = (W - s - 80) // 16 * 16
         short = ref.deepclean_forward(p, x[:, :, a2:], layers)[0]
         assert np.max(np.abs(short[-s:] - full[-s:])) > 1e-8
+
+
+# ------------------------------------------------- aggregation latency (App. B)
+
+def test_golden_delayed_clean():
+    g = GOLD["delayed_clean"]
+    seg, clean = ref.delayed_clean(np.array(g["noise"], float)[None], np.array(g["strain_seg"], float)[None],
+                                   g["delay"])
+    np.testing.assert_array_equal(seg[0], g["segment"])
+    np.testing.assert_array_equal(clean[0], g["clean"])
+
+
+def test_delayed_clean_reduces_to_causal_at_zero_delay():
+    rng = np.random.default_rng(5)
+    noise, st = rng.standard_normal((3, 64)), rng.standard_normal((3, 8))
+    a = ref.delayed_clean(noise, st, 0)
+    b = ref.causal_clean(noise, st)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("W,s,delay", [(64, 8, 0), (64, 8, 24), (64, 8, 56), (48, 5, 13)])
+def test_delayed_clean_absolute_time(W, s, delay):
+    """Brute force over absolute sample times: windows cut from one noise
+    series f(u) (window k ends at t_k = k s + W) and one strain series g(u);
+    request k's output must be g(u) - f(u) for u in [t_k - s - delay,
+    t_k - delay), i.e. the same span of both series."""
+    rng = np.random.default_rng(W + s + delay)
+    K = 6
+    f = rng.standard_normal(K * s + W)
+    g = rng.standard_normal(K * s + W)
+    for k in range(K):
+        t = k * s + W
+        window = f[t - W:t][None]
+        span = np.arange(t - s - delay, t - delay)
+        seg, clean = ref.delayed_clean(window, g[span][None], delay)
+        np.testing.assert_array_equal(seg[0], f[span])
+        np.testing.assert_array_equal(clean[0], g[span] - f[span])
+
+
+def test_delayed_clean_range():
+    with pytest.raises(ValueError):
+        ref.delayed_clean(np.zeros((1, 16)), np.zeros((1, 4)), 13)
