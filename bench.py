@@ -395,6 +395,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-band", action="store_true")
+    ap.add_argument("--no-agg", action="store_true", help="skip the output aggregation variants")
     ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
     ap.add_argument("--dc-cus", type=int, default=224,
                     help="CU budget of the fused DeepClean kernel (0: all CUs); the CUs left over run the "
@@ -486,11 +487,11 @@ def main():
     s_main, s_bb = torch.cuda.current_stream(), torch.cuda.Stream()
     ev_in, ev_bb = torch.cuda.Event(), torch.cuda.Event()
 
-    def run_models(k, flags):
+    def run_models(k, flags, delays=None):
         ev_in.record(s_main)
         s_bb.wait_event(ev_in)
         dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
-                   precision=prec, ws=ws_dc, flags=flags)
+                   precision=prec, ws=ws_dc, flags=flags, delays=delays)
         bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
         ev_bb.record(s_bb)
         s_main.wait_event(ev_bb)
@@ -505,6 +506,13 @@ def main():
         k += 1
     torch.cuda.synchronize()
     log("bench: warmup done")
+    # the host loop allocates small Python objects per call; a full cyclic
+    # collection over the live objects would stall it for tens of ms, so
+    # the timed and latency loops run with the collector frozen (the calls
+    # create no reference cycles)
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(k)
@@ -524,6 +532,8 @@ def main():
         torch.cuda.synchronize()
         lat.append(1e3 * (time.perf_counter() - t1))
         k += 1
+    gc.enable()
+    gc.unfreeze()
     lat = np.array(lat) if lat else np.zeros(1)
     log(f"bench: latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
@@ -572,6 +582,69 @@ def main():
                         "clean output bitwise equal to the full-window recompute"}
         log(f"bench: causal band {band['value']:.4g} samples/s, {band['ms_per_step']:.3f} ms/step, "
             f"p99 {band['p99_ms']:.3f} ms")
+
+    # output aggregation variants (App. B): a 0.75-s aggregation latency on
+    # every DeepClean stream (causal band reaching back s + delay), and the
+    # average of each output over the 4 latest overlapping predictions (full
+    # noise windows, then deepclean_overlap_average with per-stream state)
+    agg = None
+    if not args.no_agg and prec == gs.BF16:
+        delay = int(0.75 * 4096)
+        dls = np.full(N_DC, delay, np.int32)
+        depth = 4
+        noise_full = torch.empty((N_DC, DC_W), device=dev)
+        ws_full = torch.empty(dc.workspace_bytes(N_DC, DC_W, prec), dtype=torch.uint8, device=dev)
+        state = torch.zeros(dc.overlap_state_floats(dc_s, depth), device=dev)
+        cnt = [0]
+
+        def step_delay(k):
+            pool.update(slots, strides, staged[k], offsets)
+            run_models(k, gs.CAUSAL, dls)
+
+        def step_avg(k):
+            pool.update(slots, strides, staged[k], offsets)
+            ev_in.record(s_main)
+            s_bb.wait_event(ev_in)
+            dc.forward(pool=pool, slots=dc_sl, W=DC_W, noise=noise_full, precision=prec, ws=ws_full)
+            dc.overlap_average(noise=noise_full, strides=dc_s, depth=depth, counts=[cnt[0]] * N_DC, state=state,
+                               strain=staged_strain[k], clean=clean)
+            cnt[0] += 1
+            bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
+            ev_bb.record(s_bb)
+            s_main.wait_event(ev_bb)
+
+        agg = {}
+        for name, fn in (("delay_0.75s_band", step_delay), ("overlap_average_depth4", step_avg)):
+            ka = 0
+            for _ in range(args.warmup):
+                fn(ka % n_steps_total)
+                ka += 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn(ka % n_steps_total)
+                ka += 1
+            torch.cuda.synchronize()
+            dta = time.perf_counter() - t0
+            agg[name] = {"value": step_samples * args.steps / dta, "unit": "samples/s",
+                         "ms_per_step": 1e3 * dta / args.steps}
+            log(f"bench: aggregation {name}: {agg[name]['value']:.4g} samples/s, "
+                f"{agg[name]['ms_per_step']:.3f} ms/step")
+        gs.profile_begin()
+        for _ in range(5):
+            step_avg(ka % n_steps_total)
+            ka += 1
+        prof_a = gs.profile_end()
+        if "overlap_average" in prof_a:
+            c_, t_ = prof_a["overlap_average"]
+            # per launch: read the windows' last depth*s samples, read+write the
+            # state, read strain, write clean
+            by = 4.0 * float(np.sum(dc_s)) * (depth + 2 * depth + 2)
+            agg["overlap_average_kernel"] = {"avg_us": 1e3 * t_ / c_, "algorithmic_bytes": by,
+                                             "achieved_GBs": by / (t_ / c_ * 1e-3) / 1e9}
+        agg["note"] = ("delay: clean = strain - noise[W-s-d, W-d) with d = 3072 samples (0.75 s), causal band; "
+                       "average: full noise windows, then the mean over the 4 latest predictions of each sample")
+        del noise_full, ws_full, state
 
     roof = None
     if not args.no_roofline:
@@ -675,7 +748,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "bbhnet_batches": bbh_batches, "deepclean_1s_fp32": d0,
-        "fp32_plain": plain, "causal_band": band, "serving": serving, "training": training, "roofline": roof,
+        "fp32_plain": plain, "causal_band": band, "aggregation": agg, "serving": serving, "training": training, "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -233,6 +233,35 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
                       void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * deepclean_overlap_average: aggregation of overlapping predictions (App.
+ * B.2: the output segments of successive windows overlap and, unlike the
+ * inputs, differ; averaging them trades latency for quality).  With depth N,
+ * request k of a stream with stride s outputs the s samples that lie
+ * (N - 1) s to N s samples before its newest sample, averaged over the
+ * predictions of windows k - N + 1 .. k (of those that exist: min(N, k + 1)
+ * windows), i.e. the mean of noise_{k-i}[W - (N - i) s + t], i = 0..N-1.
+ * N = 1 is the fully-online output.  Latency grows by (N - 1) s samples.
+ *   n, W, strides host [n] (1 <= s_i, N s_i <= W), counts host [n]: k_i,
+ *   the number of earlier requests of item i's stream passed through this
+ *   call (0 for its first request);
+ *   noise  device [n][W] float32: this request's predicted windows (the
+ *          noise output of deepclean_forward);
+ *   state  device float32, caller-owned, packed per item: item i's block
+ *          of N s_i floats starts at the prefix sum of N s_j over j < i; it
+ *          must be zero before a stream's first request and is carried from
+ *          one request of the stream to the next (same N and s);
+ *   strain device packed [s_i] (with clean): the strain samples of the
+ *          output span; clean device packed [s_i] = strain - average; avg
+ *          device packed [s_i] = the averaged noise.  Either may be NULL,
+ *          not both.
+ * Errors: GW_EINVAL (null pointers, sizes), GW_ESTATE (not a DeepClean
+ * model; the model's staging ring carries the item table).
+ */
+int deepclean_overlap_average(const gw_model* model, int32_t n, int32_t W, const int32_t* strides, int32_t depth,
+                              const int64_t* counts, const float* noise, float* state, const float* strain,
+                              float* clean, float* avg, void* hip_stream);
+
+/*
  * deepclean_backward (retraining): gradient of a scalar loss with respect to
  * the flat parameter vector, given dnoise = dL/dnoise (device [n][W] float32)
  * for the batch-statistics forward that filled `saved` (the ws of a

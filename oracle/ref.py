@@ -268,6 +268,26 @@ def causal_clean(noise, strain_new):
     return tail, np.asarray(strain_new, np.float64) - tail
 
 
+def overlap_average(windows, s, depth):
+    """Aggregation of overlapping predictions (App. B.2: successive output
+    segments overlap and differ; averaging them costs latency).  windows
+    [K][W]: the predictions of requests 0..K-1 of one stream with stride s,
+    window k ending at t_k = t_0 + k s.  Output k covers the absolute span
+    [t_k - depth s, t_k - (depth - 1) s), which every window k - i, i = 0..
+    depth-1, contains at positions W - (depth - i) s .. W - (depth - 1 - i) s;
+    it is the mean over the windows among those that exist (k - i >= 0).
+    depth = 1 is the fully-online tail.  -> [K][s]."""
+    w = np.asarray(windows, np.float64)
+    K, W = w.shape
+    if not (s >= 1 and depth >= 1 and depth * s <= W):
+        raise ValueError("need 1 <= s and depth * s <= W")
+    out = np.zeros((K, s))
+    for k in range(K):
+        terms = [w[k - i, W - (depth - i) * s: W - (depth - 1 - i) * s] for i in range(depth) if k - i >= 0]
+        out[k] = np.mean(terms, axis=0)
+    return out
+
+
 def delayed_clean(noise, strain_seg, delay):
     """Aggregation latency (App. B, "Aggregation latency"): the newest
     `delay` predicted samples of each window are dropped as edge-degraded;

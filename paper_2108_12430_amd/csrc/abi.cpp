@@ -1075,6 +1075,42 @@ int bw_layout(const gw_model* m, int n, int W, uint32_t flags, BwWs& b) {
 
 }  // namespace
 
+extern "C" int deepclean_overlap_average(const gw_model* m, int32_t n, int32_t W, const int32_t* strides,
+                                         int32_t depth, const int64_t* counts, const float* noise, float* state,
+                                         const float* strain, float* clean, float* avg, void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  if (n == 0) return GW_OK;
+  if (n < 0 || W < 1 || depth < 1) return fail(GW_EINVAL, "need n >= 0, W >= 1, depth >= 1");
+  if (!strides || !counts || !noise || !state) return fail(GW_EINVAL, "null argument");
+  if (!clean && !avg) return fail(GW_EINVAL, "no output requested");
+  if (clean && !strain) return fail(GW_EINVAL, "clean output needs strain");
+  std::vector<Item> items(n);
+  int64_t off = 0, soff = 0;
+  int max_s = 1;
+  for (int i = 0; i < n; ++i) {
+    const int s = strides[i];
+    if (s < 1 || (int64_t)depth * s > W) return fail(GW_EINVAL, "stride must be in [1, W / depth]");
+    if (counts[i] < 0) return fail(GW_EINVAL, "negative request count");
+    Item& it = items[i];
+    std::memset(&it, 0, sizeof(it));
+    it.s = s;
+    it.out = off;
+    it.src = soff;
+    it.head = (int)(counts[i] % depth);
+    it.C = (int)std::min<int64_t>(depth, counts[i] + 1);
+    off += s;
+    soff += (int64_t)depth * s;
+    max_s = std::max(max_s, s);
+  }
+  const Item* dev_items = nullptr;
+  CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items));
+  LAUNCH("overlap_average", st,
+         gw::launch_overlap_average(dev_items, n, max_s, W, depth, noise, state, strain, clean, avg, st));
+  return GW_OK;
+}
+
 extern "C" int deepclean_backward_scratch(const gw_model* m, int32_t n, int32_t W, uint32_t flags,
                                           size_t* bytes) {
   if (!m || !bytes) return fail(GW_EINVAL, "null argument");

@@ -200,3 +200,45 @@ hipError_t launch_gap_finalize(const float* part, int nblk, const float* bias, f
 }
 
 }  // namespace gw
+
+namespace gw {
+
+// Overlap averaging of successive predictions of one stream (App. B.2 notes
+// that the output segments of successive windows overlap and could be
+// aggregated).  Item fields: s = stride, out = offset of the item's packed
+// [s] output block, src = offset (floats) of its state block [depth][s],
+// head = request index k mod depth, C = windows averaged, min(depth, k + 1).
+// State slot j accumulates the output of the request whose index is j mod
+// depth.  Window k contributes to outputs k .. k + depth - 1: to output k + i
+// its samples at W - (depth - i) s + t.  One thread per output sample t, so
+// the depth slots of a sample are updated by one thread in order.
+__global__ __launch_bounds__(256) void overlap_average_kernel(const Item* items, int W, int depth,
+                                                              const float* noise, float* state,
+                                                              const float* strain, float* clean, float* avg) {
+  const Item it = items[blockIdx.y];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= it.s) return;
+  const float* P = noise + (int64_t)blockIdx.y * W;
+  float* R = state + it.src;
+  for (int i = 0; i < depth; ++i) {
+    int slot = it.head + i;
+    if (slot >= depth) slot -= depth;
+    R[(int64_t)slot * it.s + t] += P[W - (depth - i) * it.s + t];
+  }
+  float* r0 = R + (int64_t)it.head * it.s + t;
+  const float v = *r0 / (float)it.C;
+  *r0 = 0.0f;  // the slot starts over for output k + depth
+  const int64_t o = it.out + t;
+  if (avg) avg[o] = v;
+  if (clean) clean[o] = strain[o] - v;
+}
+
+hipError_t launch_overlap_average(const Item* items, int n, int max_s, int W, int depth, const float* noise,
+                                  float* state, const float* strain, float* clean, float* avg, hipStream_t st) {
+  dim3 grid((unsigned)((max_s + 255) / 256), (unsigned)n);
+  hipLaunchKernelGGL(overlap_average_kernel, grid, dim3(256), 0, st, items, W, depth, noise, state, strain, clean,
+                     avg);
+  return hipGetLastError();
+}
+
+}  // namespace gw

@@ -27,7 +27,8 @@ EXPORTS = [
     "gw_last_error", "gw_pool_init", "gw_pool_free", "gw_stream_open", "gw_stream_close",
     "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
-    "deepclean_workspace", "deepclean_forward", "deepclean_backward_scratch", "deepclean_backward",
+    "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "deepclean_backward_scratch",
+    "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "bbhnet_workspace", "bbhnet_forward",
     "gw_profile_begin", "gw_profile_end",
 ]
@@ -70,6 +71,7 @@ def lib():
             "gw_model_n_params": ([i32, vp, i32, P(i64)], C.c_int),
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
+            "deepclean_overlap_average": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "deepclean_backward_scratch": ([vp, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_backward": ([vp, i32, i32, vp, vp, vp, vp, u32, i32, vp, sz, vp], C.c_int),
             "gw_bandpass_workspace": ([i32, i32, f32, f32, f32, P(sz)], C.c_int),
@@ -297,6 +299,23 @@ class DeepClean(_Model):
                                       _ptr(strain), _ptr(noise), _ptr(clean), precision, flags, _ptr(ws),
                                       ws.numel(), _stream(stream)))
         return ws
+
+    @staticmethod
+    def overlap_state_floats(strides, depth):
+        """Floats of the caller-owned state overlap_average needs."""
+        return int(depth) * int(np.sum(np.asarray(strides, np.int64)))
+
+    def overlap_average(self, *, noise, strides, depth, counts, state, strain=None, clean=None, avg=None,
+                        stream=None):
+        """Enqueue deepclean_overlap_average for n = noise.shape[0] items."""
+        _f32(noise, "noise")
+        _f32(state, "state")
+        n, W = noise.shape
+        st, pst = _host_i32(strides)
+        cn = np.ascontiguousarray(counts, dtype=np.int64)
+        check(lib().deepclean_overlap_average(self.h, n, W, pst, int(depth), cn.ctypes.data_as(C.c_void_p),
+                                              _ptr(noise), _ptr(state), _ptr(strain), _ptr(clean), _ptr(avg),
+                                              _stream(stream)))
 
     def backward_scratch_bytes(self, n, W, flags):
         b = C.c_size_t()

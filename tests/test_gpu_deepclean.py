@@ -476,3 +476,82 @@ def test_aggregation_delay_rejected(dc):
             m.forward(x=x, strides=[256, 256], delays=bad, strain=strain, clean=clean, precision=gs.BF16)
     with pytest.raises(gs.GwError):     # delays without a clean output
         m.forward(x=x, noise=torch.empty((2, W), device=DEV), delays=[0, 0], precision=gs.BF16)
+
+
+def test_overlap_average_kernel(dc):
+    """Overlap averaging against the oracle on synthetic prediction windows:
+    three streams with different strides, eight successive requests (the
+    first depth - 1 average fewer windows), state carried on the device."""
+    m, _, _ = dc
+    W, depth, K = 1024, 3, 8
+    strides = [64, 256, 100]
+    n = len(strides)
+    wins = [synth.gaussian(40 + i, (K, W)) for i in range(n)]
+    strain = [synth.gaussian(60 + i, (K, s)) for i, s in enumerate(strides)]
+    state = torch.zeros(m.overlap_state_floats(strides, depth), device=DEV)
+    exp = [ref.overlap_average(wins[i], s, depth) for i, s in enumerate(strides)]
+    for k in range(K):
+        noise = torch.from_numpy(np.stack([wins[i][k] for i in range(n)])).to(DEV)
+        st = torch.from_numpy(np.concatenate([strain[i][k] for i in range(n)])).to(DEV)
+        avg = torch.empty(sum(strides), device=DEV)
+        clean = torch.empty(sum(strides), device=DEV)
+        m.overlap_average(noise=noise, strides=strides, depth=depth, counts=[k] * n, state=state, strain=st,
+                          clean=clean, avg=avg)
+        torch.cuda.synchronize()
+        a, c = avg.cpu().numpy(), clean.cpu().numpy()
+        o = 0
+        for i, s in enumerate(strides):
+            assert rel(a[o:o + s], exp[i][k]) <= FP32_TOL, (k, i)
+            assert rel(c[o:o + s], strain[i][k] - exp[i][k]) <= FP32_TOL, (k, i)
+            o += s
+
+
+def test_overlap_average_streaming(dc):
+    """End to end: ring-resident streams, BF16 forward of every request's
+    window, then overlap averaging (depth 4), against the oracle forward of
+    the same snapshots averaged by the oracle.  The BF16 bound holds for the
+    predicted windows (2e-2 of their largest magnitude); a mean over
+    sub-spans of them keeps that absolute bound, so the averaged output is
+    checked against 2e-2 of the windows' scale, not of its own span's."""
+    m, params, layers = dc
+    W, depth, K, s = 4096, 4, 6, 256
+    n = 2
+    pool = gs.Pool(64 << 20, max_slots=4, max_items=4)
+    slots = [pool.open(21, W) for _ in range(n)]
+    data = [synth.witness_stream(800 + i, W + K * s)[0] for i in range(n)]
+    for i in range(n):
+        pool.update([slots[i]], [W], torch.from_numpy(np.ascontiguousarray(data[i][:, :W])).to(DEV).reshape(-1),
+                    [0])
+    state = torch.zeros(m.overlap_state_floats([s] * n, depth), device=DEV)
+    ws = torch.empty(m.workspace_bytes(n, W, gs.BF16), dtype=torch.uint8, device=DEV)
+    got = np.zeros((n, K, s))
+    snaps = np.zeros((n, K, 21, W))
+    for k in range(K):
+        blocks = np.concatenate([np.ascontiguousarray(data[i][:, W + k * s:W + (k + 1) * s]).reshape(-1)
+                                 for i in range(n)])
+        pool.update(slots, [s] * n, torch.from_numpy(blocks).to(DEV), [0, 21 * s])
+        noise = torch.empty((n, W), device=DEV)
+        m.forward(pool=pool, slots=slots, W=W, noise=noise, precision=gs.BF16, ws=ws)
+        avg = torch.empty(n * s, device=DEV)
+        m.overlap_average(noise=noise, strides=[s] * n, depth=depth, counts=[k] * n, state=state, avg=avg)
+        torch.cuda.synchronize()
+        got[:, k] = avg.cpu().numpy().reshape(n, s)
+        for i in range(n):
+            snaps[i, k] = data[i][:, (k + 1) * s:(k + 1) * s + W]
+    for i in range(n):
+        wins = ref.deepclean_forward(params, snaps[i], layers)
+        exp = ref.overlap_average(wins, s, depth)
+        assert np.max(np.abs(got[i] - exp)) <= BF16_TOL * np.max(np.abs(wins)), i
+
+
+def test_overlap_average_rejected(dc):
+    m, _, _ = dc
+    noise = torch.zeros((1, 64), device=DEV)
+    state = torch.zeros(64, device=DEV)
+    avg = torch.empty(32, device=DEV)
+    with pytest.raises(gs.GwError):     # depth * s > W
+        m.overlap_average(noise=noise, strides=[32], depth=3, counts=[0], state=state, avg=avg)
+    with pytest.raises(gs.GwError):     # no output
+        m.overlap_average(noise=noise, strides=[32], depth=2, counts=[0], state=state)
+    with pytest.raises(gs.GwError):     # negative count
+        m.overlap_average(noise=noise, strides=[32], depth=2, counts=[-1], state=state, avg=avg)

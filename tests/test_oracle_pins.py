@@ -485,3 +485,52 @@ def test_delayed_clean_absolute_time(W, s, delay):
 def test_delayed_clean_range():
     with pytest.raises(ValueError):
         ref.delayed_clean(np.zeros((1, 16)), np.zeros((1, 4)), 13)
+
+
+# --------------------------------------- overlap averaging of predictions (App. B.2)
+
+def test_golden_overlap_average():
+    g = GOLD["overlap_average"]
+    got = ref.overlap_average(np.array(g["windows"], float), g["s"], g["depth"])
+    np.testing.assert_array_equal(got, g["out"])
+
+
+def test_overlap_average_depth_one_is_causal_tail():
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal((5, 64))
+    got = ref.overlap_average(w, 8, 1)
+    np.testing.assert_array_equal(got, ref.causal_clean(w, np.zeros((5, 8)))[0])
+
+
+@pytest.mark.parametrize("W,s,depth", [(64, 8, 3), (64, 16, 4), (48, 5, 9), (40, 4, 1)])
+def test_overlap_average_absolute_time(W, s, depth):
+    """Brute force over absolute time: every prediction of every window is
+    filed under its absolute sample time; output k must be, for each sample
+    of its span [t_k - depth s, t_k - (depth - 1) s), the mean of the
+    predictions filed there by windows max(0, k - depth + 1) .. k.  Windows
+    cut from one series f give f itself."""
+    rng = np.random.default_rng(W * s + depth)
+    K = 7
+    windows = rng.standard_normal((K, W))
+    filed = {}
+    for j in range(K):
+        t = j * s + W
+        for p in range(W):
+            filed.setdefault(t - W + p, {})[j] = windows[j, p]
+    got = ref.overlap_average(windows, s, depth)
+    for k in range(K):
+        t = k * s + W
+        for q, u in enumerate(range(t - depth * s, t - (depth - 1) * s)):
+            vals = [filed[u][j] for j in range(max(0, k - depth + 1), k + 1)]
+            assert abs(got[k, q] - np.mean(vals)) <= 1e-12 * max(1.0, np.abs(vals).max())
+    f = rng.standard_normal(K * s + W)
+    same = np.stack([f[j * s: j * s + W] for j in range(K)])
+    got = ref.overlap_average(same, s, depth)
+    for k in range(K):
+        t = k * s + W
+        np.testing.assert_allclose(got[k], f[t - depth * s: t - (depth - 1) * s], rtol=1e-14, atol=1e-14)
+
+
+def test_overlap_average_range():
+    with pytest.raises(ValueError):
+        ref.overlap_average(np.zeros((2, 16)), 5, 4)
