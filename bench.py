@@ -396,6 +396,7 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--no-agg", action="store_true", help="skip the output aggregation variants")
+    ap.add_argument("--no-ens", action="store_true", help="skip the end-to-end ensemble leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
     ap.add_argument("--dc-cus", type=int, default=224,
                     help="CU budget of the fused DeepClean kernel (0: all CUs); the CUs left over run the "
@@ -646,6 +647,43 @@ def main():
                        "average: full noise windows, then the mean over the 4 latest predictions of each sample")
         del noise_full, ws_full, state
 
+    # end-to-end ensemble (main text, second offline workflow): per request,
+    # both detectors' witness rings, DeepClean-H1 and -L1 with the clean
+    # output, decimation to 2048 Hz into the BBHnet ring, BBHnet logits
+    ens = None
+    if not args.no_ens and prec == gs.BF16:
+        from paper_2108_12430_amd import ensemble
+        n_e, s_e = 64, 256
+        dc_l1 = gs.DeepClean(torch.from_numpy(synth.deepclean_params(1)).to(dev), layers)
+        dc.set_cu_budget(0)  # one stream: nothing runs beside the DeepClean kernels
+        e = ensemble.Ensemble(dc, dc_l1, bb, n_e, W_dc=DC_W, W_bb=BB_W, stride=s_e, precision=prec)
+        g = torch.Generator(device="cpu").manual_seed(11)
+        e.prefill(torch.randn((2, n_e, DC_C, DC_W), generator=g).to(dev))
+        wits = [torch.randn((2, n_e, DC_C, s_e), generator=g).to(dev) for _ in range(8)]
+        sts = [torch.randn((2, n_e, s_e), generator=g).to(dev) for _ in range(8)]
+        for k in range(args.warmup):
+            e.step(wits[k % 8], sts[k % 8])
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            e.step(wits[k % 8], sts[k % 8])
+        torch.cuda.synchronize()
+        dte = time.perf_counter() - t0
+        gc.enable()
+        gc.unfreeze()
+        ms_e = 1e3 * dte / args.steps
+        ens = {"streams": n_e, "stride": s_e, "ms_per_step": ms_e,
+               "strain_samples_per_s": 2 * n_e * s_e / (ms_e * 1e-3),
+               "data_seconds_per_s": n_e * s_e / 4096 / (ms_e * 1e-3),
+               "config": f"{n_e} ensemble streams: 2 x (21 x {DC_W}) witness snapshots at 4096 Hz, "
+                         f"BBHnet 2 x {BB_W} at 2048 Hz, {s_e} new samples per request"}
+        log(f"bench: ensemble {ms_e:.3f} ms/step, {ens['data_seconds_per_s']:.1f} s of data per s")
+        del e, dc_l1, wits, sts
+        dc.set_cu_budget(args.dc_cus)
+
     roof = None
     if not args.no_roofline:
         gs.profile_begin()
@@ -748,7 +786,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "bbhnet_batches": bbh_batches, "deepclean_1s_fp32": d0,
-        "fp32_plain": plain, "causal_band": band, "aggregation": agg, "serving": serving, "training": training, "roofline": roof,
+        "fp32_plain": plain, "causal_band": band, "aggregation": agg, "ensemble": ens, "serving": serving, "training": training, "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

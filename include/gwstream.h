@@ -233,6 +233,27 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
                       void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * gw_decimate2: streaming decimation by 2 with a causal FIR, the step of the
+ * end-to-end ensemble (main text, second offline workflow; its figure of the
+ * ensemble) that takes the two detectors' cleaned 4096 Hz strain to BBHnet's
+ * 2048 Hz input: y[m] = sum_j taps[j] x[2m + 1 - j] over each channel's
+ * stream of samples (zero before the first).  n items (streams) with C
+ * channels, all with the same even stride s (new input samples per call):
+ *   taps  device [ntaps] float32, 1 <= ntaps <= 257;
+ *   x     device [C][n][s] float32: channel c of item i at (c n + i) s (two
+ *         deepclean_forward clean outputs of equal strides, one after the
+ *         other, are this layout for C = 2);
+ *   hist  device [n][C][ntaps - 1] float32, caller-owned: the inputs before
+ *         this call's, oldest first; zero at a stream's start; advanced by
+ *         the call;
+ *   y     device [n][C][s / 2] float32: the s / 2 new outputs, item by item
+ *         in the [C][s/2] block layout snapshot_update reads.
+ * Errors: GW_EINVAL for sizes or null pointers.
+ */
+int gw_decimate2(int32_t n, int32_t C, int32_t s, int32_t ntaps, const float* taps, const float* x, float* hist,
+                 float* y, void* hip_stream);
+
+/*
  * deepclean_overlap_average: aggregation of overlapping predictions (App.
  * B.2: the output segments of successive windows overlap and, unlike the
  * inputs, differ; averaging them trades latency for quality).  With depth N,

@@ -381,3 +381,62 @@ def mse(strain, noise):
     r = np.asarray(strain, np.float64) - np.asarray(noise, np.float64)
     B, W = r.shape
     return float(np.sum(r * r) / (B * W)), -2.0 / (B * W) * r
+
+
+# ---------------------------------------------------------------------------
+# End-to-end ensemble (main text, second offline workflow and its ensemble
+# figure): one snapshotter for three sources, DeepClean per detector, the
+# cleaned strain combined and resampled to BBHnet's rate, BBHnet logits.
+# ---------------------------------------------------------------------------
+
+def lowpass_taps(K, fc):
+    """Windowed-sinc low-pass FIR (a reading of the ensemble's unspecified
+    "postprocess" before resampling): h[j] = 2 fc sinc(2 fc (j - (K-1)/2))
+    times a Hann window of length K, scaled to unit DC gain; fc in cycles per
+    input sample."""
+    j = np.arange(K, dtype=np.float64)
+    c = j - (K - 1) / 2.0
+    h = 2.0 * fc * np.sinc(2.0 * fc * c)
+    w = 0.5 - 0.5 * np.cos(2.0 * np.pi * (j + 1) / (K + 1))
+    h = h * w
+    return h / h.sum()
+
+
+def decimate2(x, taps):
+    """Causal FIR then every second sample: y[m] = sum_j h[j] x[2m + 1 - j],
+    with x zero before its first sample.  x [..., U] (U even) -> [..., U/2]."""
+    x = np.asarray(x, np.float64)
+    h = np.asarray(taps, np.float64)
+    U = x.shape[-1]
+    y = np.zeros(x.shape[:-1] + (U // 2,))
+    for m in range(U // 2):
+        for j in range(len(h)):
+            v = 2 * m + 1 - j
+            if v >= 0:
+                y[..., m] += h[j] * x[..., v]
+    return y
+
+
+def ensemble_logits(dc_params, witness, strain, bbh_params, taps, s, W_dc, W_bb, K,
+                    dc_layers=DEEPCLEAN_LAYERS, bbh_stages=BBHNET_STAGES):
+    """K requests of one ensemble stream (stride s at the DeepClean rate).
+    witness [2][C][U], strain [2][U] per detector (H1, L1), U = W_dc + K s;
+    the detectors' snapshots start full (the first W_dc samples), request k
+    adds samples [W_dc + k s, W_dc + (k+1) s).  Per request: each detector's
+    DeepClean on its snapshot, fully-online clean block (causal_clean), the
+    two cleaned streams decimated by 2 (decimate2 over everything cleaned so
+    far), BBHnet on the snapshot of the decimated stream (W_bb samples, zero
+    before its start).  Returns logits [K]."""
+    cleaned = np.zeros((2, K * s))
+    logits = np.zeros(K)
+    for k in range(K):
+        end = W_dc + (k + 1) * s
+        for d in range(2):
+            snap = snapshot_after(witness[d], end, W_dc)
+            noise = deepclean_forward(dc_params[d], snap[None], dc_layers)
+            _, cl = causal_clean(noise, strain[d][None, end - s:end])
+            cleaned[d, k * s:(k + 1) * s] = cl[0]
+        dec = decimate2(cleaned[:, :(k + 1) * s], taps)
+        bsnap = snapshot_after(dec, dec.shape[-1], W_bb)
+        logits[k] = bbhnet_forward(bbh_params, bsnap[None], bbh_stages)[0]
+    return logits

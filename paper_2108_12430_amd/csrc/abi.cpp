@@ -1075,6 +1075,18 @@ int bw_layout(const gw_model* m, int n, int W, uint32_t flags, BwWs& b) {
 
 }  // namespace
 
+extern "C" int gw_decimate2(int32_t n, int32_t C, int32_t s, int32_t ntaps, const float* taps, const float* x,
+                            float* hist, float* y, void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (n == 0) return GW_OK;
+  if (n < 0 || C < 1 || C > 65535) return fail(GW_EINVAL, "need n >= 0 and 1 <= C <= 65535");
+  if (s < 2 || s % 2) return fail(GW_EINVAL, "stride must be even and positive");
+  if (ntaps < 1 || ntaps > 257) return fail(GW_EINVAL, "ntaps must be in [1, 257]");
+  if (!taps || !x || !y || (ntaps > 1 && !hist)) return fail(GW_EINVAL, "null argument");
+  LAUNCH("decimate2", st, gw::launch_decimate2(n, C, s, ntaps, taps, x, hist, y, st));
+  return GW_OK;
+}
+
 extern "C" int deepclean_overlap_average(const gw_model* m, int32_t n, int32_t W, const int32_t* strides,
                                          int32_t depth, const int64_t* counts, const float* noise, float* state,
                                          const float* strain, float* clean, float* avg, void* hip_stream) {

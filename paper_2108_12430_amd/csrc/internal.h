@@ -91,6 +91,8 @@ hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k
 hipError_t launch_snapshot(void* arena, const Item* items, int n, int max_cs, const float* samples,
                            hipStream_t st);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_decimate2(int n, int C, int s, int K, const float* taps, const float* x, float* hist, float* y,
+                            hipStream_t st);
 hipError_t launch_overlap_average(const Item* items, int n, int max_s, int W, int depth, const float* noise,
                                   float* state, const float* strain, float* clean, float* avg, hipStream_t st);
 hipError_t launch_zero_floats(float* dst, int64_t n, hipStream_t st);

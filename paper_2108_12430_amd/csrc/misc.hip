@@ -242,3 +242,44 @@ hipError_t launch_overlap_average(const Item* items, int n, int max_s, int W, in
 }
 
 }  // namespace gw
+
+namespace gw {
+
+// Streaming decimation by 2 with a causal FIR (the end-to-end ensemble's
+// step from the cleaned 4096 Hz strain to BBHnet's 2048 Hz input):
+// y[m] = sum_j h[j] x[2m + 1 - j] over the stream's samples, zero before its
+// first.  One block per (item, channel); the K - 1 inputs before the new
+// block come from the item's history, which the block then advances.
+__global__ __launch_bounds__(256) void decimate2_kernel(int n, int s, int K, const float* taps, const float* x,
+                                                        float* hist, float* y) {
+  const int i = blockIdx.x, c = blockIdx.y, C = gridDim.y;
+  const float* xb = x + ((int64_t)c * n + i) * s;           // the s new samples
+  float* hb = hist + ((int64_t)i * C + c) * (K - 1);        // the K - 1 before them, oldest first
+  float* yb = y + ((int64_t)i * C + c) * (s / 2);
+  for (int m = threadIdx.x; m < s / 2; m += 256) {
+    float acc = 0.0f;
+    for (int j = 0; j < K; ++j) {
+      const int v = 2 * m + 1 - j;  // input index relative to the new block
+      acc = fmaf(taps[j], v >= 0 ? xb[v] : hb[K - 1 + v], acc);
+    }
+    yb[m] = acc;
+  }
+  // next history: the last K - 1 samples of (history, block); read before
+  // any thread writes (K - 1 <= 256: one sample per thread)
+  float h = 0.0f;
+  const int e = threadIdx.x;
+  if (e < K - 1) {
+    const int v = s - (K - 1) + e;
+    h = v >= 0 ? xb[v] : hb[K - 1 + v];
+  }
+  __syncthreads();
+  if (e < K - 1) hb[e] = h;
+}
+
+hipError_t launch_decimate2(int n, int C, int s, int K, const float* taps, const float* x, float* hist, float* y,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(decimate2_kernel, dim3((unsigned)n, (unsigned)C), dim3(256), 0, st, n, s, K, taps, x, hist, y);
+  return hipGetLastError();
+}
+
+}  // namespace gw

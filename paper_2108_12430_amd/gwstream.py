@@ -27,7 +27,8 @@ EXPORTS = [
     "gw_last_error", "gw_pool_init", "gw_pool_free", "gw_stream_open", "gw_stream_close",
     "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
-    "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "deepclean_backward_scratch",
+    "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
+    "deepclean_backward_scratch",
     "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "bbhnet_workspace", "bbhnet_forward",
     "gw_profile_begin", "gw_profile_end",
@@ -72,6 +73,7 @@ def lib():
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
             "deepclean_overlap_average": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "gw_decimate2": ([i32, i32, i32, i32, vp, vp, vp, vp, vp], C.c_int),
             "deepclean_backward_scratch": ([vp, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_backward": ([vp, i32, i32, vp, vp, vp, vp, u32, i32, vp, sz, vp], C.c_int),
             "gw_bandpass_workspace": ([i32, i32, f32, f32, f32, P(sz)], C.c_int),
@@ -376,6 +378,15 @@ def bandpass_mse(strain, noise, fs=4096.0, f_lo=55.0, f_hi=65.0, want_grad=True,
     check(lib().gw_bandpass_mse(n, W, fs, f_lo, f_hi, _ptr(_f32(strain, "strain")), _ptr(_f32(noise, "noise")),
                                 _ptr(loss), _ptr(dn), _ptr(ws), ws.numel(), _stream(stream)))
     return loss, dn
+
+
+def decimate2(*, x, taps, hist, y, stream=None):
+    """Enqueue gw_decimate2.  x [C][n][s], hist [n][C][ntaps - 1] (state),
+    y [n][C][s / 2]; all float32 device tensors."""
+    for t, nm in ((x, "x"), (taps, "taps"), (hist, "hist"), (y, "y")):
+        _f32(t, nm)
+    C_, n, s = x.shape
+    check(lib().gw_decimate2(n, C_, s, taps.numel(), _ptr(taps), _ptr(x), _ptr(hist), _ptr(y), _stream(stream)))
 
 
 def profile_begin():

@@ -534,3 +534,58 @@ def test_overlap_average_absolute_time(W, s, depth):
 def test_overlap_average_range():
     with pytest.raises(ValueError):
         ref.overlap_average(np.zeros((2, 16)), 5, 4)
+
+
+# ------------------------------------------------ end-to-end ensemble pieces
+
+def test_decimate2_hand_worked():
+    # y[m] = sum_j h[j] x[2m + 1 - j]: y0 = 0.5*2 + 0.25*1, y1 = 0.5*4 + 0.25*3 + 0.25*2
+    y = ref.decimate2(np.array([1.0, 2.0, 3.0, 4.0]), np.array([0.5, 0.25, 0.25]))
+    np.testing.assert_array_equal(y, [1.25, 3.25])
+
+
+@pytest.mark.parametrize("U,K", [(64, 7), (200, 63), (10, 31)])
+def test_decimate2_is_convolution_then_every_second(U, K):
+    rng = np.random.default_rng(U + K)
+    x = rng.standard_normal((3, U))
+    h = rng.standard_normal(K)
+    want = np.stack([np.convolve(r, h)[1:U:2] for r in x])
+    np.testing.assert_allclose(ref.decimate2(x, h), want, rtol=1e-12, atol=1e-12)
+
+
+def test_lowpass_taps_response():
+    """Unit DC gain, linear phase (symmetric), passband flat and stopband
+    (above the 1024 Hz output Nyquist, in cycles per 4096-Hz input sample:
+    0.25) attenuated."""
+    h = ref.lowpass_taps(63, 0.225)
+    assert abs(h.sum() - 1.0) < 1e-14
+    np.testing.assert_allclose(h, h[::-1], rtol=0, atol=1e-16)
+    resp = lambda f: abs(np.sum(h * np.exp(-2j * np.pi * f * np.arange(63))))
+    assert all(abs(resp(f) - 1.0) < 2e-2 for f in (0.01, 0.05, 0.1, 0.15))
+    assert all(resp(f) < 1e-2 for f in (0.3, 0.35, 0.4, 0.45, 0.5))
+
+
+def test_product_lowpass_taps_match_the_oracle():
+    from paper_2108_12430_amd import ensemble
+    np.testing.assert_allclose(ensemble.lowpass_taps(63, 0.225), ref.lowpass_taps(63, 0.225), rtol=0, atol=1e-15)
+
+
+def test_ensemble_wiring_with_silent_deepclean():
+    """With all-zero DeepClean parameters the predicted noise is zero, so the
+    cleaned strain is the strain itself: the ensemble's logits must be BBHnet
+    on the snapshot of the decimated strain of the requests so far."""
+    from paper_2108_12430_amd import synth
+    s, W_dc, W_bb, K = 64, 256, 512, 4
+    n_dc = len(synth.deepclean_params(0))
+    zero = [np.zeros(n_dc), np.zeros(n_dc)]
+    rng = np.random.default_rng(3)
+    U = W_dc + K * s
+    witness = rng.standard_normal((2, 21, 21, U))[:, 0]      # [2][21][U]
+    strain = rng.standard_normal((2, U))
+    bbp = synth.bbhnet_params(0)
+    taps = ref.lowpass_taps(15, 0.225)
+    got = ref.ensemble_logits(zero, witness, strain, bbp, taps, s, W_dc, W_bb, K)
+    for k in range(K):
+        dec = ref.decimate2(strain[:, W_dc:W_dc + (k + 1) * s], taps)
+        want = ref.bbhnet_forward(bbp, ref.snapshot_after(dec, dec.shape[-1], W_bb)[None])[0]
+        assert abs(got[k] - want) <= 1e-12 * max(1.0, abs(want))
