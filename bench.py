@@ -488,11 +488,11 @@ def main():
     s_main, s_bb = torch.cuda.current_stream(), torch.cuda.Stream()
     ev_in, ev_bb = torch.cuda.Event(), torch.cuda.Event()
 
-    def run_models(k, flags, delays=None):
+    def run_models(k, flags, delays=None, dc_prec=None):
         ev_in.record(s_main)
         s_bb.wait_event(ev_in)
         dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
-                   precision=prec, ws=ws_dc, flags=flags, delays=delays)
+                   precision=prec if dc_prec is None else dc_prec, ws=ws_dc, flags=flags, delays=delays)
         bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
         ev_bb.record(s_bb)
         s_main.wait_event(ev_bb)
@@ -614,8 +614,13 @@ def main():
             ev_bb.record(s_bb)
             s_main.wait_event(ev_bb)
 
+        def step_f16(k):
+            pool.update(slots, strides, staged[k], offsets)
+            run_models(k, 0, dc_prec=gs.FP16)
+
         agg = {}
-        for name, fn in (("delay_0.75s_band", step_delay), ("overlap_average_depth4", step_avg)):
+        for name, fn in (("delay_0.75s_band", step_delay), ("overlap_average_depth4", step_avg),
+                         ("deepclean_fp16", step_f16)):
             ka = 0
             for _ in range(args.warmup):
                 fn(ka % n_steps_total)
@@ -644,7 +649,8 @@ def main():
             agg["overlap_average_kernel"] = {"avg_us": 1e3 * t_ / c_, "algorithmic_bytes": by,
                                              "achieved_GBs": by / (t_ / c_ * 1e-3) / 1e9}
         agg["note"] = ("delay: clean = strain - noise[W-s-d, W-d) with d = 3072 samples (0.75 s), causal band; "
-                       "average: full noise windows, then the mean over the 4 latest predictions of each sample")
+                       "average: full noise windows, then the mean over the 4 latest predictions of each sample; "
+                       "deepclean_fp16: the main step with FP16 operands in the fused DeepClean kernel")
         del noise_full, ws_full, state
 
     # end-to-end ensemble (main text, second offline workflow): per request,

@@ -59,6 +59,10 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define GW_FP32 0          /* FP32 direct convolution on the vector ALUs        */
 #define GW_BF16 1          /* BF16 MFMA implicit GEMM, FP32 accumulate/epilogue */
+#define GW_FP16 2          /* FP16 operands in the fused DeepClean kernel (the
+                              reference network's inference only; the precision
+                              the paper served DeepClean in); else
+                              GW_EUNSUPPORTED */
 
 #define GW_MODEL_DEEPCLEAN 1
 #define GW_MODEL_BBHNET 2

@@ -381,6 +381,7 @@ struct LayerD {
   int64_t w, b, g, be, m, v;  // parameter offsets (floats)
   size_t scale, shift;        // packed byte offsets
   size_t wbf;                 // packed bf16 weights byte offset
+  size_t wf16;                // packed fp16 weights byte offset (fused-shape networks)
   bool bf16;                  // BF16 kernel available
 };
 
@@ -487,6 +488,11 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
       }
       m.fused = m.bf16_all && gw::dc_fused_supported(ci.data(), co.data(), ty.data(), k.data(), st.data(),
                                                      pd.data(), op.data(), bn.data(), Ln);
+      if (m.fused)
+        for (auto& ly : m.layers) {  // FP16 copies for the fused kernel's FP16 variant
+          ly.wf16 = pk;
+          pk += r256(2 * gw::conv_bf16_packed_elems(ly.ci, ly.co, ly.k, ly.type == GW_LAYER_CONVT));
+        }
     }
   } else if (kind == GW_MODEL_BBHNET) {
     const int Sn = desc[0];
@@ -552,6 +558,9 @@ int pack_model(gw_model* m, hipStream_t st) {
       if (ly.bf16)
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf), ly.ci,
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st));
+      if (m->fused)
+        HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wf16), ly.ci,
+                                    ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, true));
     }
   } else {
     for (auto& sd : m->stages) {
@@ -832,8 +841,10 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   if (n < 0) return fail(GW_EINVAL, "negative n");
   if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
   if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
-  if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
+  if (precision != GW_FP32 && precision != GW_BF16 && precision != GW_FP16) return fail(GW_EINVAL, "bad precision");
   if (flags & ~(GW_TRAIN | GW_RECOMPUTE | GW_CAUSAL | GW_LAYERWISE)) return fail(GW_EINVAL, "bad flags");
+  if (precision == GW_FP16 && (!m->fused || (flags & (GW_TRAIN | GW_LAYERWISE))))
+    return fail(GW_EUNSUPPORTED, "FP16 is the fused kernel's variant: reference network, inference only");
   if ((flags & GW_CAUSAL) && (flags & GW_TRAIN)) return fail(GW_EINVAL, "GW_CAUSAL is for inference");
   if ((flags & GW_CAUSAL) && (!clean || noise))
     return fail(GW_EINVAL, "GW_CAUSAL computes only the clean output (noise must be NULL)");
@@ -916,7 +927,8 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
   char* wsb = reinterpret_cast<char*>(ws);
   const int L = (int)m->layers.size();
   const void* arena = pool ? pool->arena : nullptr;
-  if (!(flags & GW_TRAIN) && precision == GW_BF16 && m->fused && !(flags & GW_LAYERWISE)) {
+  const bool f16 = precision == GW_FP16;
+  if (!(flags & GW_TRAIN) && (precision == GW_BF16 || f16) && m->fused && !(flags & GW_LAYERWISE)) {
     // whole network in one kernel, activations on chip
     gw::ConvP p{};
     p.n = n;
@@ -931,11 +943,12 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
     const float* sc[9];
     const float* sh[9];
     for (int l = 0; l < 9; ++l) {
-      wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + m->layers[l].wbf);
+      wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + (f16 ? m->layers[l].wf16 : m->layers[l].wbf));
       sc[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].scale);
       sh[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].shift);
     }
-    LAUNCH("dc_fused_bf16", st, gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, m->cu_budget, st));
+    LAUNCH(f16 ? "dc_fused_f16" : "dc_fused_bf16", st,
+           gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, m->cu_budget, st, f16));
     return GW_OK;
   }
   if (!(flags & GW_TRAIN)) {
@@ -1145,6 +1158,7 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
   if (!x || !dnoise || !saved || !dparams || !scratch) return fail(GW_EINVAL, "null argument");
   if (!(flags & GW_TRAIN) || (flags & ~(GW_TRAIN | GW_RECOMPUTE)))
     return fail(GW_EINVAL, "flags must be GW_TRAIN or GW_TRAIN|GW_RECOMPUTE (as in the forward)");
+  if (precision == GW_FP16) return fail(GW_EUNSUPPORTED, "FP16 is an inference variant");
   if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
   if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
   DcWs w;
@@ -1350,6 +1364,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
   if ((pool != nullptr) == (x != nullptr)) return fail(GW_EINVAL, "exactly one of pool and x must be given");
   if (pool && !slots) return fail(GW_EINVAL, "pool input needs slots");
   if (!logits || !ws) return fail(GW_EINVAL, "null logits or workspace");
+  if (precision == GW_FP16) return fail(GW_EUNSUPPORTED, "no FP16 BBHnet kernels");
   if (precision != GW_FP32 && precision != GW_BF16) return fail(GW_EINVAL, "bad precision");
   if (precision == GW_BF16 && !m->bf16_all) return fail(GW_EUNSUPPORTED, "no BF16 kernel for this network");
   BbWs b;

@@ -37,7 +37,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-enum InFmt { IN_F32 = 0, IN_BF16 = 1, IN_RING = 2 };
+enum InFmt { IN_F32 = 0, IN_BF16 = 1, IN_RING = 2, IN_RING_F32 = 3 };  // IN_RING_F32: fused FP16 kernel only
 
 // Geometry of the polyphase/strided column view of a layer (host + device).
 struct Geo {
@@ -83,7 +83,7 @@ static inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
 
 __global__ void pack_bf16_kernel(const float* w, uint16_t* out, int Ci, int Co, int k, int s, int p,
                                  bool tr, int nph, int kt, int padc, int MT, int KS, int CIP,
-                                 int total) {
+                                 int total, bool f16) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
   const int e = idx & 7;
@@ -106,7 +106,7 @@ __global__ void pack_bf16_kernel(const float* w, uint16_t* out, int Ci, int Co, 
       if (j >= 0 && j < k) v = w[((int64_t)i * Co + o) * k + j];
     }
   }
-  out[idx] = bf16_rne(v);
+  out[idx] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)v) : bf16_rne(v);
 }
 
 static void frag_dims(int Ci, int Co, int k, int s, int p, bool tr, int* MT, int* KS, int* CIP,
@@ -126,14 +126,14 @@ size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool tr) {
 }
 
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool tr,
-                            hipStream_t st) {
+                            hipStream_t st, bool f16) {
   const int s = tr ? 2 : 1, p = 3;
   int MT, KS, CIP;
   Geo g;
   frag_dims(Ci, Co, k, s, p, tr, &MT, &KS, &CIP, &g);
   const int total = g.nph * MT * KS * 512;
   hipLaunchKernelGGL(pack_bf16_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, Ci, Co, k, s,
-                     p, tr, g.nph, g.kt, g.padc, MT, KS, CIP, total);
+                     p, tr, g.nph, g.kt, g.padc, MT, KS, CIP, total, f16);
   return hipGetLastError();
 }
 
@@ -933,12 +933,42 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
 }
 
+// Two floats -> packed IEEE half pair (round to nearest even), first in the
+// low half.
+__device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi) {
+  typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, f16x2_t));
+}
+
+// The fused kernel's 16-bit element type: BF16 (default) or FP16.
+template <bool F16>
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  if constexpr (F16)
+    return pack_f16x2(lo, hi);
+  else
+    return pack_bf16x2(lo, hi);
+}
+
+// 16x16x32 MFMA on 8 packed 16-bit values per lane, FP32 accumulation
+template <bool F16>
+__device__ __forceinline__ f32x4 mfma16(const uint4& a, const uint4& b, const f32x4& c) {
+  if constexpr (F16) {
+    typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  }
+}
+
 // BN + tanh of channels o0..o0+3 of one output row of layer l (scale and
 // shift pre-multiplied by 2 log2 e), stored as four bf16 in one 8 B LDS
 // write.  Positions outside the layer's signal are stored as zeros (the next
 // layer's padding); only tiles at a window edge (EDGE) have any.  Every
 // C_out here is a multiple of 8, so no stored channel is padding.
-template <int l, bool EDGE>
+template <int l, bool EDGE, bool F16>
 __device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v, float4 sc, float4 sh, int pos0,
                                         int Lout) {
   using namespace fused;
@@ -956,11 +986,11 @@ __device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v,
     t3 = live ? t3 : 0.0f;
   }
   const int prow = HO ? (row & 1) * HO + (row >> 1) : row;
-  *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(pack_bf16x2(t0, t1), pack_bf16x2(t2, t3));
+  *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(pack2<F16>(t0, t1), pack2<F16>(t2, t3));
 }
 
 // Epilogue of one work unit (see fused_layer).
-template <int l, bool EDGE, int NTCl, int Q>
+template <int l, bool EDGE, int NTCl, int Q, bool F16>
 __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, int sp, int lc, int lg, uint16_t* out,
                                           const float* ksc, const float* ksh, int pos0, int Lout, const ConvP* op,
                                           int b, int Wout) {
@@ -1006,13 +1036,13 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
             v[r] = __uint_as_float(__builtin_amdgcn_permlane32_swap(__float_as_uint(acc[a][ph][r]),
                                                                     __float_as_uint(acc[a + 1][ph][r]), false,
                                                                     false)[0]);
-          epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, v, sc4, sh4, pos0, Lout);
+          epi_row<l, EDGE, F16>(out, P == 1 ? c : 2 * c + ph - 1, o0, v, sc4, sh4, pos0, Lout);
         }
       } else if (lg < 2) {
         const int c = (nt0 + a) * 16 + lc;
 #pragma unroll
         for (int ph = 0; ph < P; ++ph)
-          epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][ph], sc4, sh4, pos0, Lout);
+          epi_row<l, EDGE, F16>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][ph], sc4, sh4, pos0, Lout);
       }
     }
   } else {
@@ -1028,7 +1058,7 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
       for (int a = 0; a < NTCl; ++a) {
         if (nt0 + a >= NTn) break;
         const int c = (nt0 + a) * 16 + lc;
-        epi_row<l, EDGE>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][k], sc4, sh4, pos0, Lout);
+        epi_row<l, EDGE, F16>(out, P == 1 ? c : 2 * c + ph - 1, o0, acc[a][k], sc4, sh4, pos0, Lout);
       }
     }
   }
@@ -1040,7 +1070,7 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
 // weight fragments (at most 16, 64 VGPRs) from global memory before its first
 // MFMA; the 92 KB of packed weights stay in L2, shared by every block.  kt
 // holds the layer's row of the B-offset table.
-template <int l>
+template <int l, bool F16>
 __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
                                             const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
                                             const ConvP* op, int b, int Wout) {
@@ -1085,16 +1115,15 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
 #pragma unroll
       for (int a = 0; a < NTCl; ++a) {
         if (nt0 + a >= NTn) break;  // wave-uniform
-        const bf16x8 bb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + a * 16 * SX * RSI));
+        const uint4 bb = *reinterpret_cast<const uint4*>(src + a * 16 * SX * RSI);
 #pragma unroll
-        for (int k = 0; k < Q; ++k)
-          acc[a][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[k][ks]), bb, acc[a][k], 0, 0, 0);
+        for (int k = 0; k < Q; ++k) acc[a][k] = mfma16<F16>(__builtin_bit_cast(uint4, af[k][ks]), bb, acc[a][k]);
       }
     }
     if (edge)
-      fused_epi<l, true, NTCl, Q>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
+      fused_epi<l, true, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
     else
-      fused_epi<l, false, NTCl, Q>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
+      fused_epi<l, false, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
   }
 }
 
@@ -1116,7 +1145,7 @@ constexpr int XITEMS = cdiv(XG * XCH, NTHR);       // items per thread
 
 template <int IN>
 struct XRaw {
-  static constexpr int NV = IN == IN_F32 ? 2 : 1;  // 16 B pieces per channel chunk
+  static constexpr int NV = IN == IN_F32 || IN == IN_RING_F32 ? 2 : 1;  // 16 B pieces per channel chunk
   u32x4 v[fused::XITEMS][4][NV];
 };
 
@@ -1126,12 +1155,19 @@ template <int IN>
 __device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint16_t* hrow, const float* frow,
                                            int head, int ld, int Lin, int qc, bool vec) {
   constexpr int NV = XRaw<IN>::NV;
+  constexpr bool F32SRC = IN == IN_F32 || IN == IN_RING_F32;
 #pragma unroll
   for (int k = 0; k < NV; ++k) d[k] = u32x4{0u, 0u, 0u, 0u};
   if (vec && qc >= 0 && qc + 8 <= Lin) {
     if (IN == IN_F32) {
       d[0] = *reinterpret_cast<const u32x4*>(frow + qc);
       d[NV - 1] = *reinterpret_cast<const u32x4*>(frow + qc + 4);
+    } else if (IN == IN_RING_F32) {
+      // an aligned 8-sample chunk never straddles the ring's wrap point
+      int ph = head + qc;
+      if (ph >= ld) ph -= ld;
+      d[0] = *reinterpret_cast<const u32x4*>(frow + ph);
+      d[NV - 1] = *reinterpret_cast<const u32x4*>(frow + ph + 4);
     } else {
       int ph = qc;
       if (IN == IN_RING) {
@@ -1149,6 +1185,10 @@ __device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint1
       if (q >= 0 && q < Lin) {
         if (IN == IN_F32) {
           w[e] = __float_as_uint(frow[q]);
+        } else if (IN == IN_RING_F32) {
+          int ph = head + q;
+          if (ph >= ld) ph -= ld;
+          w[e] = __float_as_uint(frow[ph]);
         } else {
           int ph = q;
           if (IN == IN_RING) {
@@ -1159,7 +1199,7 @@ __device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint1
         }
       }
     }
-    if (IN == IN_F32) {
+    if (F32SRC) {
       d[0] = u32x4{w[0], w[1], w[2], w[3]};
       d[NV - 1] = u32x4{w[4], w[5], w[6], w[7]};
     } else {
@@ -1185,6 +1225,12 @@ __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q
     ld = it.W;
     hbase = reinterpret_cast<const uint16_t*>(p.arena) + it.shadow;
     vec = (ld & 7) == 0 && (head & 7) == 0 && (it.shadow & 7) == 0;
+  } else if (IN == IN_RING_F32) {
+    const Item& it = p.items[b];
+    head = it.head;
+    ld = it.W;
+    fbase = reinterpret_cast<const float*>(p.arena) + it.ring;
+    vec = (ld & 7) == 0 && (head & 7) == 0 && (it.ring & 3) == 0;
   } else {
     fbase = p.x + (int64_t)b * Ci * ld;
     vec = (ld & 7) == 0 && (reinterpret_cast<uintptr_t>(p.x) & 15) == 0;
@@ -1199,15 +1245,16 @@ __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q
       const int i = 4 * g + k;
       const bool on = ch < nch && i < Ci;
       const int64_t ro = (int64_t)(on ? i : 0) * ld;
-      load_chunk<IN>(R.v[it][k], hbase + (IN == IN_RING ? ro : 0), fbase + (IN == IN_F32 ? ro : 0), head, ld,
+      load_chunk<IN>(R.v[it][k], hbase + (IN == IN_RING ? ro : 0), fbase + (IN != IN_RING ? ro : 0), head, ld,
                      on ? Lin : 0, qc, vec);
     }
   }
 }
 
 // Write the staged rows to LDS (row stride RS, even/odd split at HALF).
-template <int IN>
+template <int IN, bool F16>
 __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q0) {
+  static_assert(!(F16 && IN == IN_RING), "the ring's 16-bit shadow is BF16");
   using namespace fused;
   constexpr int RS = rs(C[0]), H = HALF(0), ROWS = NR[0];
   static_assert(H > 0, "layer 0 reads its input with stride 2");
@@ -1222,12 +1269,12 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
     uint32_t c[4][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (IN == IN_F32) {
+      if (IN == IN_F32 || IN == IN_RING_F32) {
         const u32x4 a = R.v[it][k][0], z = R.v[it][k][XRaw<IN>::NV - 1];
-        c[k][0] = pack_bf16x2(__uint_as_float(a.x), __uint_as_float(a.y));
-        c[k][1] = pack_bf16x2(__uint_as_float(a.z), __uint_as_float(a.w));
-        c[k][2] = pack_bf16x2(__uint_as_float(z.x), __uint_as_float(z.y));
-        c[k][3] = pack_bf16x2(__uint_as_float(z.z), __uint_as_float(z.w));
+        c[k][0] = pack2<F16>(__uint_as_float(a.x), __uint_as_float(a.y));
+        c[k][1] = pack2<F16>(__uint_as_float(a.z), __uint_as_float(a.w));
+        c[k][2] = pack2<F16>(__uint_as_float(z.x), __uint_as_float(z.y));
+        c[k][3] = pack2<F16>(__uint_as_float(z.z), __uint_as_float(z.w));
       } else {
         const u32x4 a = R.v[it][k][0];
         c[k][0] = a.x; c[k][1] = a.y; c[k][2] = a.z; c[k][3] = a.w;
@@ -1256,7 +1303,7 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
 #ifndef GW_FUSED_WAVES_PER_SIMD
 #define GW_FUSED_WAVES_PER_SIMD 6
 #endif
-template <int IN>
+template <int IN, bool F16>
 __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused(ConvP p, FusedP f, int ntile) {
   using namespace fused;
   __shared__ __attribute__((aligned(16))) uint16_t bufA[BUFA];
@@ -1287,7 +1334,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     }
   }
   // input tile rows [u0 - 93, u0 + T + 93) in [time][channel] layout
-  store_x<IN>(bufA, raw, (t0 % tpw) * T + LO[0]);
+  store_x<IN, F16>(bufA, raw, (t0 % tpw) * T + LO[0]);
   __syncthreads();
 
   for (int t = t0; t < t1; ++t) {
@@ -1301,7 +1348,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     {                                                                                                       \
       int tid = threadIdx.x;                                                                                \
       asm volatile("" : "+v"(tid));                                                                         \
-      fused_layer<l>(tid, IN_BUF, OUT_BUF, reinterpret_cast<const uint4*>(f.wpk[l]), &ktab[l][0][0],       \
+      fused_layer<l, F16>(tid, IN_BUF, OUT_BUF, reinterpret_cast<const uint4*>(f.wpk[l]), &ktab[l][0][0],       \
                      ksc[l], ksh[l], u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);             \
       __syncthreads();                                                                                      \
     }
@@ -1319,7 +1366,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
       // the next tile's input: the other block on the CU hides its latency
       const int nq = ((t + 1) % tpw) * T + LO[0];
       load_x<IN>(raw, p, (t + 1) / tpw, nq);
-      store_x<IN>(bufA, raw, nq);
+      store_x<IN, F16>(bufA, raw, nq);
       __syncthreads();
     }
   }
@@ -1341,7 +1388,8 @@ bool dc_fused_supported(const int* ci, const int* co, const int* type, const int
 // p: n, items (ring input or clean outputs), arena, x (+ ldx), noise, clean,
 // strain; W = window (or band) length, a multiple of 16.
 hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
-                                const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st) {
+                                const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
+                                bool f16) {
   using namespace fused;
   if (W < 16 || W % 16) return hipErrorInvalidValue;
   FusedP f;
@@ -1366,24 +1414,23 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
   const int64_t ntile = (int64_t)p.n * ((W + T - 1) / T);
   if (ntile > (int64_t)1 << 30) return hipErrorInvalidValue;
   // one resident grid: (blocks per CU) x CUs, at most one block per tile
-  static int occ[2] = {0, 0}, cus = 0;
-  const int v = ring ? 1 : 0;
+  // variants: (ring or dense input) x (BF16 or FP16); the FP16 variant reads
+  // the ring's FP32 samples (its 16-bit shadow is BF16)
+  void (*kern[4])(ConvP, FusedP, int) = {dc_fused<IN_F32, false>, dc_fused<IN_RING, false>,
+                                         dc_fused<IN_F32, true>, dc_fused<IN_RING_F32, true>};
+  static int occ[4] = {0, 0, 0, 0}, cus = 0;
+  const int v = (ring ? 1 : 0) + (f16 ? 2 : 0);
   if (!occ[v]) {
     int dev = 0, n = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-      e = ring ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dc_fused<IN_RING>, NTHR, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dc_fused<IN_F32>, NTHR, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern[v], NTHR, 0);
     if (e != hipSuccess) return e;
     occ[v] = n > 0 ? n : 1;
   }
   const int ncu = cu_budget > 0 && cu_budget < cus ? cu_budget : cus;
   const int64_t grid = std::min<int64_t>(ntile, (int64_t)occ[v] * ncu);
-  if (ring)
-    hipLaunchKernelGGL(dc_fused<IN_RING>, dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
-  else
-    hipLaunchKernelGGL(dc_fused<IN_F32>, dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
+  hipLaunchKernelGGL(kern[v], dim3((unsigned)grid), dim3(NTHR), 0, st, q, f, (int)ntile);
   return hipGetLastError();
 }
 

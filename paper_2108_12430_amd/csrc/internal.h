@@ -83,10 +83,12 @@ int conv_bf16_gap_parts(int Ci, int Co, int Lout, int n);  // GAP partial sums p
 bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,
                         const int* pad, const int* op, const int* bn, int L);
 hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
-                                const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st);
+                                const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
+                                bool f16 = false);
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
+// f16: IEEE half (round to nearest even) instead of bf16
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool transposed,
-                            hipStream_t st);
+                            hipStream_t st, bool f16 = false);
 
 hipError_t launch_snapshot(void* arena, const Item* items, int n, int max_cs, const float* samples,
                            hipStream_t st);

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgwstream.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_ESTATE, GW_EHIP, GW_EUNSUPPORTED = range(6)
-FP32, BF16 = 0, 1
+FP32, BF16, FP16 = 0, 1, 2
 MODEL_DEEPCLEAN, MODEL_BBHNET = 1, 2
 TRAIN, RECOMPUTE, CAUSAL, LAYERWISE = 1, 2, 4, 8
 _CODES = {1: "GW_EINVAL", 2: "GW_ENOMEM", 3: "GW_ESTATE", 4: "GW_EHIP", 5: "GW_EUNSUPPORTED"}

@@ -26,7 +26,7 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # bench launch name -> rocprof kernel name, for the kernels whose traffic
 # bench.py reports
 KERNELS = {
-    "dc_fused_bf16": "void gw::dc_fused<2>(gw::ConvP, gw::FusedP, int)",
+    "dc_fused_bf16": "void gw::dc_fused<2, false>(gw::ConvP, gw::FusedP, int)",
     "snapshot": "gw::snapshot_kernel(char*, gw::Item const*, float const*)",
 }
 SOURCE = "paper_2108_12430_amd/csrc/conv_bf16.hip"

@@ -555,3 +555,76 @@ def test_overlap_average_rejected(dc):
         m.overlap_average(noise=noise, strides=[32], depth=2, counts=[0], state=state)
     with pytest.raises(gs.GwError):     # negative count
         m.overlap_average(noise=noise, strides=[32], depth=2, counts=[-1], state=state, avg=avg)
+
+
+# ---------------------------------------------------------------- FP16 variant
+FP16_TOL = 2.5e-3   # the BF16 bound scaled by the ratio of the unit roundoffs (2^-11 / 2^-8)
+
+
+@pytest.mark.parametrize("W,n", [(32768, 2), (4096, 3), (16 * 67, 2), (16, 1)])
+def test_forward_fp16(dc, W, n):
+    """FP16 operands in the fused kernel (FP32 accumulation and epilogue):
+    within the FP16 bound of the oracle and at least 4x closer than BF16 on
+    the same input (full tiles, a ragged last tile, the shortest window)."""
+    m, params, layers = dc
+    x = synth.gaussian(620 + W, (n, 21, W))
+    xt = torch.from_numpy(x).to(DEV)
+    a = torch.empty((n, W), device=DEV)
+    b = torch.empty((n, W), device=DEV)
+    m.forward(x=xt, noise=a, precision=gs.FP16)
+    m.forward(x=xt, noise=b, precision=gs.BF16)
+    torch.cuda.synchronize()
+    exp = ref.deepclean_forward(params, x, layers)
+    e16, ebf = rel(a.cpu().numpy(), exp), rel(b.cpu().numpy(), exp)
+    assert e16 <= FP16_TOL
+    assert e16 * 4 <= ebf
+
+
+def test_fp16_ring_equals_dense_and_causal(dc):
+    """The FP16 kernel reads the rings' FP32 samples (wrapping at each ring's
+    head): outputs from rings equal those from the same windows passed
+    densely, bitwise; GW_CAUSAL gives the full-window clean output bitwise."""
+    m, params, layers = dc
+    W, strides = 4096, [256, 1, 1024, 512]
+    n = len(strides)
+    pool = gs.Pool(64 << 20, max_slots=8, max_items=8)
+    slots = [pool.open(21, W) for _ in range(n)]
+    wit, strain_all = synth.witness_stream(91, W + 3000)
+    for i in range(n):
+        fill = W // 2 + 997 * i + 3          # heads not multiples of 8 for some rings
+        sofar = 0
+        while sofar < fill:
+            s = min(W, fill - sofar)
+            pool.update([slots[i]], [s], torch.from_numpy(np.ascontiguousarray(wit[:, sofar:sofar + s])).to(DEV)
+                        .reshape(-1), [0])
+            sofar += s
+    strain = torch.from_numpy(np.concatenate([strain_all[:s] for s in strides])).to(DEV)
+    noise_r = torch.empty((n, W), device=DEV)
+    full = torch.empty(sum(strides), device=DEV)
+    band = torch.empty(sum(strides), device=DEV)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, strain=strain, clean=full, noise=noise_r,
+              precision=gs.FP16)
+    m.forward(pool=pool, slots=slots, W=W, strides=strides, strain=strain, clean=band, precision=gs.FP16,
+              flags=gs.CAUSAL)
+    xs = torch.stack([pool.window(sl) for sl in slots]).contiguous()
+    noise_d = torch.empty((n, W), device=DEV)
+    m.forward(x=xs, noise=noise_d, precision=gs.FP16)
+    torch.cuda.synchronize()
+    assert torch.equal(noise_r, noise_d)
+    assert torch.equal(full, band)
+    exp = ref.deepclean_forward(params, xs.cpu().numpy().astype(np.float64), layers)
+    assert rel(noise_r.cpu().numpy(), exp) <= FP16_TOL
+
+
+def test_fp16_unsupported_paths(dc):
+    m, _, _ = dc
+    x = torch.zeros((1, 21, 4096), device=DEV)
+    noise = torch.empty((1, 4096), device=DEV)
+    for flags in (gs.LAYERWISE, gs.TRAIN):
+        with pytest.raises(gs.GwError) as e:
+            m.forward(x=x, noise=noise, precision=gs.FP16, flags=flags)
+        assert e.value.code == gs.GW_EUNSUPPORTED
+    bbm = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(DEV), synth.bbhnet_stages())
+    with pytest.raises(gs.GwError) as e:
+        bbm.forward(x=torch.zeros((1, 2, 2048), device=DEV), precision=gs.FP16)
+    assert e.value.code == gs.GW_EUNSUPPORTED
