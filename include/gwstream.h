@@ -219,7 +219,8 @@ int deepclean_workspace(const gw_model* model, int32_t n, int32_t W, int32_t pre
  *          d_i samples).  Item i's clean block is then strain - noise[W - s_i
  *          - d_i .. W - d_i), and its strain block holds the s_i strain
  *          samples that end d_i samples before the window's newest sample.
- * precision GW_FP32 or GW_BF16.  flags: 0 (inference, running statistics),
+ * precision GW_FP32, GW_BF16, or GW_FP16 (reference network, inference,
+ * fused kernel only; GW_EUNSUPPORTED otherwise).  flags: 0 (inference, running statistics),
  * GW_TRAIN (batch statistics over n*time per channel; requires x),
  * GW_TRAIN|GW_RECOMPUTE, or GW_CAUSAL (inference, clean output only; the
  * band is chosen from the largest s_i + d_i and aligned to the network's total
