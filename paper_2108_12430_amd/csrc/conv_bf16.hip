@@ -810,11 +810,11 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
 namespace gw {
 
 // ===========================================================================
-// Fused DeepClean forward (BF16).  One block computes T consecutive output
-// samples of one window through all nine layers; every intermediate
-// activation stays in LDS.  Working backwards from the output tile [u0, u0+T)
-// each layer's needed output positions are a fixed range around its scaled
-// tile start (see kFused below); the input tile is the window's samples
+// Fused DeepClean forward (BF16 or FP16 operands, FP32 accumulation).  One
+// block computes T consecutive output samples of one window through all nine
+// layers; every intermediate activation stays in LDS.  Working backwards from
+// the output tile [u0, u0+T) each layer's needed output positions are a fixed
+// range around its scaled tile start (LO and NR below); the input tile is the window's samples
 // [u0 - 93, u0 + T + 93) (the receptive field).  Positions outside a layer's
 // signal are stored as zeros, i.e. they are the next layer's zero padding, so
 // every output equals the layer-by-layer result up to summation order.
