@@ -17,7 +17,11 @@ second, the BF16 batched path), per-update latency p50/p99 (request ready ->
 result complete, synchronous pass), the same workload on the FP32 plain path
 (one stream at a time, FP32 direct convolution), the dominant kernel's
 roofline figures from HIP events, and the FP64 CPU oracle on a bounded sample
-of the same requests.
+of the same requests.  Further legs, each outside `value` and skippable:
+the receptive-field band only (GW_CAUSAL), the output aggregation variants
+(0.75-s aggregation latency, depth-4 overlap averaging) and FP16 DeepClean,
+64 end-to-end ensemble streams, dense BBHnet batches, a 1-s FP32 DeepClean
+window, the retraining step, and PCIe-inclusive serving through serve.py.
 """
 from __future__ import annotations
 
