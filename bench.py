@@ -592,7 +592,7 @@ def main():
     # every DeepClean stream (causal band reaching back s + delay), and the
     # average of each output over the 4 latest overlapping predictions (full
     # noise windows, then deepclean_overlap_average with per-stream state)
-    agg = None
+    agg = precision_leg = None
     if not args.no_agg and prec == gs.BF16:
         delay = int(0.75 * 4096)
         dls = np.full(N_DC, delay, np.int32)
@@ -653,8 +653,9 @@ def main():
             agg["overlap_average_kernel"] = {"avg_us": 1e3 * t_ / c_, "algorithmic_bytes": by,
                                              "achieved_GBs": by / (t_ / c_ * 1e-3) / 1e9}
         agg["note"] = ("delay: clean = strain - noise[W-s-d, W-d) with d = 3072 samples (0.75 s), causal band; "
-                       "average: full noise windows, then the mean over the 4 latest predictions of each sample; "
-                       "deepclean_fp16: the main step with FP16 operands in the fused DeepClean kernel")
+                       "average: full noise windows, then the mean over the 4 latest predictions of each sample")
+        precision_leg = {"deepclean_fp16": agg.pop("deepclean_fp16"),
+                         "note": "the main step with FP16 operands in the fused DeepClean kernel (BBHnet BF16)"}
         del noise_full, ws_full, state
 
     # end-to-end ensemble (main text, second offline workflow): per request,
@@ -796,7 +797,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "bbhnet_batches": bbh_batches, "deepclean_1s_fp32": d0,
-        "fp32_plain": plain, "causal_band": band, "aggregation": agg, "ensemble": ens, "serving": serving, "training": training, "roofline": roof,
+        "fp32_plain": plain, "causal_band": band, "aggregation": agg, "precision": precision_leg, "ensemble": ens, "serving": serving, "training": training, "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
