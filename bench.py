@@ -38,6 +38,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N_CUS = 256  # MI355X compute units
+
+
+class Cycle(list):
+    """A list indexed modulo its length (staged inputs reused in turn)."""
+
+    def __getitem__(self, k):
+        return list.__getitem__(self, k % len(self))
 METRIC = "streamed samples/sec + p99 per-update latency, BF16 batched vs FP32 plain"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
@@ -386,8 +393,8 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16")
     ap.add_argument("--lat-steps", type=int, default=300)
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -460,7 +467,9 @@ def main():
     wit_t = torch.from_numpy(wit).to(dev)
     strain_t = torch.from_numpy(strain).to(dev)
     bbx_t = torch.from_numpy(synth.gaussian(3, (BB_C, nsrc))).to(dev)
-    n_steps_total = args.warmup + args.steps + args.lat_steps + 4
+    # distinct staged inputs: one set per step up to 128, then reused in turn
+    # (the rings still advance every step)
+    n_steps_total = min(args.warmup + args.steps + args.lat_steps + 4, 128)
     pos = (np.arange(len(slots)) * 104729) % (nsrc // 2)
     staged, staged_strain = [], []
     for k in range(n_steps_total):
@@ -475,6 +484,7 @@ def main():
             pos[i] += s
         staged.append(torch.cat(blocks).contiguous())
         staged_strain.append(torch.cat(sblocks).contiguous())
+    staged, staged_strain = Cycle(staged), Cycle(staged_strain)
     assert staged[0].numel() == per_step_floats
     clean = torch.empty(dc_strain_len, device=dev)
     logits = torch.empty(N_BB, device=dev)
@@ -483,7 +493,7 @@ def main():
     dc_sl = np.array(dc_slots, np.int32)
     bb_sl = np.array(bb_slots, np.int32)
     torch.cuda.synchronize()
-    log(f"bench: staged {n_steps_total} steps of inputs in HBM")
+    log(f"bench: staged {n_steps_total} sets of step inputs in HBM")
 
     # the two model groups are independent after the ingest: BBHnet runs on a
     # second HIP stream (default priority) on the CUs that the DeepClean
@@ -638,7 +648,7 @@ def main():
             dta = time.perf_counter() - t0
             agg[name] = {"value": step_samples * args.steps / dta, "unit": "samples/s",
                          "ms_per_step": 1e3 * dta / args.steps}
-            log(f"bench: aggregation {name}: {agg[name]['value']:.4g} samples/s, "
+            log(f"bench: variant {name}: {agg[name]['value']:.4g} samples/s, "
                 f"{agg[name]['ms_per_step']:.3f} ms/step")
         gs.profile_begin()
         for _ in range(5):
