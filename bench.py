@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N_CUS = 256  # MI355X compute units
+ROOF_STEPS = 40  # steps whose launches the roofline pass times
 
 
 class Cycle(list):
@@ -409,9 +410,9 @@ def main():
     ap.add_argument("--no-agg", action="store_true", help="skip the output aggregation variants")
     ap.add_argument("--no-ens", action="store_true", help="skip the end-to-end ensemble leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
-    ap.add_argument("--dc-cus", type=int, default=224,
-                    help="CU budget of the fused DeepClean kernel (0: all CUs); the CUs left over run the "
-                         "BBHnet group's kernels concurrently")
+    ap.add_argument("--dc-cus", type=int, default=0,
+                    help="CU budget of the fused DeepClean kernel (0: all CUs); CUs left over run the BBHnet "
+                         "group's kernels beside it")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -495,24 +496,25 @@ def main():
     torch.cuda.synchronize()
     log(f"bench: staged {n_steps_total} sets of step inputs in HBM")
 
-    # the two model groups are independent after the ingest: BBHnet runs on a
-    # second HIP stream (default priority) on the CUs that the DeepClean
-    # kernel's budget leaves free (and on any CU once DeepClean is done); the
-    # main stream waits for it before the next ingest overwrites the rings
+    # the two model groups share no state: each runs its own ingest and
+    # forward on its own HIP stream (default priorities), so neither waits
+    # for the other; a timed loop ends with a device-wide synchronisation,
+    # i.e. when both groups have finished every step
     s_main, s_bb = torch.cuda.current_stream(), torch.cuda.Stream()
-    ev_in, ev_bb = torch.cuda.Event(), torch.cuda.Event()
+    dc_str, bb_str = strides[:N_DC], strides[N_DC:]
+    dc_off, bb_off = offsets[:N_DC], offsets[N_DC:]
+
+    def bbh_group(k):
+        pool.update(bb_sl, bb_str, staged[k], bb_off, stream=s_bb)
+        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
 
     def run_models(k, flags, delays=None, dc_prec=None):
-        ev_in.record(s_main)
-        s_bb.wait_event(ev_in)
+        pool.update(dc_sl, dc_str, staged[k], dc_off, stream=s_main)
         dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
                    precision=prec if dc_prec is None else dc_prec, ws=ws_dc, flags=flags, delays=delays)
-        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
-        ev_bb.record(s_bb)
-        s_main.wait_event(ev_bb)
+        bbh_group(k)
 
     def step(k):
-        pool.update(slots, strides, staged[k], offsets)
         run_models(k, 0)
 
     k = 0
@@ -567,7 +569,6 @@ def main():
     # fully-online output only (GW_CAUSAL): the DeepClean streams compute just
     # the band of each window that their newest samples depend on
     def step_band(k):
-        pool.update(slots, strides, staged[k], offsets)
         run_models(k, gs.CAUSAL)
 
     band = None
@@ -613,23 +614,17 @@ def main():
         cnt = [0]
 
         def step_delay(k):
-            pool.update(slots, strides, staged[k], offsets)
             run_models(k, gs.CAUSAL, dls)
 
         def step_avg(k):
-            pool.update(slots, strides, staged[k], offsets)
-            ev_in.record(s_main)
-            s_bb.wait_event(ev_in)
+            pool.update(dc_sl, dc_str, staged[k], dc_off, stream=s_main)
             dc.forward(pool=pool, slots=dc_sl, W=DC_W, noise=noise_full, precision=prec, ws=ws_full)
             dc.overlap_average(noise=noise_full, strides=dc_s, depth=depth, counts=[cnt[0]] * N_DC, state=state,
                                strain=staged_strain[k], clean=clean)
             cnt[0] += 1
-            bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
-            ev_bb.record(s_bb)
-            s_main.wait_event(ev_bb)
+            bbh_group(k)
 
         def step_f16(k):
-            pool.update(slots, strides, staged[k], offsets)
             run_models(k, 0, dc_prec=gs.FP16)
 
         agg = {}
@@ -707,9 +702,14 @@ def main():
 
     roof = None
     if not args.no_roofline:
-        gs.profile_begin()
+        # steady state, as in the timed loop: the two groups' streams are
+        # already running when the profiled steps start
         kp = 0
-        for _ in range(5):
+        for _ in range(args.warmup):
+            step(kp % n_steps_total)
+            kp += 1
+        gs.profile_begin()
+        for _ in range(ROOF_STEPS):
             step(kp % n_steps_total)
             kp += 1
         prof = gs.profile_end()
@@ -733,8 +733,8 @@ def main():
             roof["cus"] = min(args.dc_cus, N_CUS) if args.dc_cus > 0 else N_CUS
         roof["algorithmic_flops"] = flops
         roof["algorithmic_bytes"] = by
-        step_ms = sum(v[1] for v in prof.values()) / 5
-        roof["kernels_ms_per_step"] = {k2: round(v[1] / 5, 4) for k2, v in sorted(prof.items())}
+        step_ms = sum(v[1] for v in prof.values()) / ROOF_STEPS
+        roof["kernels_ms_per_step"] = {k2: round(v[1] / ROOF_STEPS, 4) for k2, v in sorted(prof.items())}
         log(f"bench: dominant kernel {name} avg {avg_s * 1e6:.1f} us; kernel sum {step_ms:.3f} ms/step")
 
     plain = None

@@ -155,3 +155,52 @@ def test_concurrent_streams_bitwise(mix):
             assert torch.equal(logits_a, logits_b)
     finally:
         dcm.set_cu_budget(0)
+
+
+def test_decoupled_group_streams_bitwise():
+    """The benchmark's step: each model group runs its own ring update and
+    forward on its own HIP stream, so the two groups never wait for each
+    other.  Three steps on two identical pools -- one driven on a single
+    stream, one with the groups on two streams -- give bitwise equal clean
+    outputs and logits at every step."""
+    nd, nb, Wd, Wb = 16, 8, 4096, 2048
+    rng = np.random.default_rng(12)
+    sd = (rng.choice([1 / 16, 1 / 8, 1 / 4], nd) * DC_FS).astype(np.int64)
+    sb = (rng.choice([1 / 16, 1 / 8, 1 / 4], nb) * BB_FS).astype(np.int64)
+    dcm = gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(DEV), synth.deepclean_layers())
+    bbm = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(DEV), synth.bbhnet_stages())
+    steps = 3
+    blocks = [torch.from_numpy(synth.gaussian(40 + k, (int(DC_C * sd.sum() + BB_C * sb.sum()),))).to(DEV)
+              for k in range(steps)]
+    strains = [torch.from_numpy(synth.gaussian(50 + k, (int(sd.sum()),))).to(DEV) for k in range(steps)]
+    offs = np.concatenate([[0], np.cumsum(np.concatenate([DC_C * sd, BB_C * sb]))[:-1]]).astype(np.int64)
+
+    def make():
+        pool = gs.Pool(64 << 20, max_slots=nd + nb, max_items=nd + nb)
+        ds = [pool.open(DC_C, Wd) for _ in range(nd)]
+        bs = [pool.open(BB_C, Wb) for _ in range(nb)]
+        return pool, ds, bs
+
+    outs = []
+    for two in (False, True):
+        pool, ds, bs = make()
+        s_main = torch.cuda.current_stream()
+        s_bb = torch.cuda.Stream() if two else s_main
+        ws_d = torch.empty(dcm.workspace_bytes(nd, Wd, gs.BF16), dtype=torch.uint8, device=DEV)
+        ws_b = torch.empty(bbm.workspace_bytes(nb, Wb, gs.BF16), dtype=torch.uint8, device=DEV)
+        res = []
+        for k in range(steps):
+            clean = torch.empty(int(sd.sum()), device=DEV)
+            logits = torch.empty(nb, device=DEV)
+            pool.update(ds, sd, blocks[k], offs[:nd], stream=s_main)
+            dcm.forward(pool=pool, slots=ds, W=Wd, strides=sd, strain=strains[k], clean=clean, precision=gs.BF16,
+                        ws=ws_d, stream=s_main)
+            pool.update(bs, sb, blocks[k], offs[nd:], stream=s_bb)
+            bbm.forward(pool=pool, slots=bs, W=Wb, logits=logits, precision=gs.BF16, ws=ws_b, stream=s_bb)
+            res.append((clean, logits))
+        torch.cuda.synchronize()
+        outs.append([(c.cpu(), l.cpu()) for c, l in res])
+    for (c1, l1), (c2, l2) in zip(*outs):
+        assert torch.equal(c1, c2)
+        assert torch.equal(l1, l2)
+        assert torch.isfinite(c1).all() and torch.isfinite(l1).all()
