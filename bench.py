@@ -409,6 +409,9 @@ def main():
     ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--no-agg", action="store_true", help="skip the output aggregation variants")
     ap.add_argument("--no-ens", action="store_true", help="skip the end-to-end ensemble leg")
+    ap.add_argument("--serial-groups", action="store_true",
+                    help="run the two model groups one after the other on one stream (the schedule the roofline "
+                         "pass times; for profiling the kernels on their own)")
     ap.add_argument("--no-extra", action="store_true", help="skip the BBHnet batch and 1-s window legs")
     ap.add_argument("--dc-cus", type=int, default=0,
                     help="CU budget of the fused DeepClean kernel (0: all CUs); CUs left over run the BBHnet "
@@ -504,18 +507,19 @@ def main():
     dc_str, bb_str = strides[:N_DC], strides[N_DC:]
     dc_off, bb_off = offsets[:N_DC], offsets[N_DC:]
 
-    def bbh_group(k):
-        pool.update(bb_sl, bb_str, staged[k], bb_off, stream=s_bb)
-        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=s_bb)
+    def bbh_group(k, st=None):
+        st = s_bb if st is None else st
+        pool.update(bb_sl, bb_str, staged[k], bb_off, stream=st)
+        bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=st)
 
-    def run_models(k, flags, delays=None, dc_prec=None):
+    def run_models(k, flags, delays=None, dc_prec=None, bb_stream=None):
         pool.update(dc_sl, dc_str, staged[k], dc_off, stream=s_main)
         dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
                    precision=prec if dc_prec is None else dc_prec, ws=ws_dc, flags=flags, delays=delays)
-        bbh_group(k)
+        bbh_group(k, bb_stream)
 
     def step(k):
-        run_models(k, 0)
+        run_models(k, 0, bb_stream=s_main if args.serial_groups else None)
 
     k = 0
     for _ in range(args.warmup):
@@ -702,15 +706,19 @@ def main():
 
     roof = None
     if not args.no_roofline:
-        # steady state, as in the timed loop: the two groups' streams are
-        # already running when the profiled steps start
+        # each kernel timed on its own: the step's two groups one after the
+        # other on one stream (in the timed loop they overlap, and a launch's
+        # duration there includes the other group's kernels on its CUs)
+        def step_serial(k):
+            run_models(k, 0, bb_stream=s_main)
+
         kp = 0
         for _ in range(args.warmup):
-            step(kp % n_steps_total)
+            step_serial(kp % n_steps_total)
             kp += 1
         gs.profile_begin()
         for _ in range(ROOF_STEPS):
-            step(kp % n_steps_total)
+            step_serial(kp % n_steps_total)
             kp += 1
         prof = gs.profile_end()
         name, (cnt, tot) = max(prof.items(), key=lambda kv: kv[1][1])
