@@ -85,3 +85,39 @@ def test_ensemble_matches_oracle(prec):
                                          taps.astype(np.float32), s, W_dc, W_bb, K) for i in range(n)])
     assert np.isfinite(got).all()
     assert rel(got, want) <= (1e-5 if prec == gs.FP32 else 2e-2)
+
+
+def test_ensemble_bench_configuration():
+    """The benchmark's ensemble launch: 64 streams, 21 x 32768 witness
+    snapshots per detector, BBHnet 2 x 2048, 256 new samples per request,
+    BF16.  Two requests; every logit finite; two sampled streams against the
+    oracle pipeline (2e-2 normwise over their logits)."""
+    n, W_dc, W_bb, s, K = 64, 32768, 2048, 256, 2
+    dcp = [synth.deepclean_params(0), synth.deepclean_params(1)]
+    bbp = synth.bbhnet_params(0)
+    layers = synth.deepclean_layers()
+    dcm = [gs.DeepClean(torch.from_numpy(p).to(DEV), layers) for p in dcp]
+    bbm = gs.BBHnet(torch.from_numpy(bbp).to(DEV), synth.bbhnet_stages())
+    taps = ref.lowpass_taps(63, 0.225)
+    ens = ensemble.Ensemble(dcm[0], dcm[1], bbm, n, W_dc=W_dc, W_bb=W_bb, stride=s, taps=taps, precision=gs.BF16)
+    U = W_dc + K * s
+    pick = (5, 50)
+    data = {i: [synth.witness_stream(2000 + 10 * i + d, U) for d in range(2)] for i in pick}
+    wit = torch.from_numpy(synth.gaussian(77, (2, n, 21, U))).to(DEV)
+    st = torch.from_numpy(synth.gaussian(78, (2, n, U))).to(DEV)
+    for i in pick:
+        for d in range(2):
+            wit[d, i] = torch.from_numpy(data[i][d][0]).to(DEV)
+            st[d, i] = torch.from_numpy(data[i][d][1]).to(DEV)
+    ens.prefill(wit[..., :W_dc].contiguous())
+    got = np.zeros((n, K))
+    for k in range(K):
+        a, b = W_dc + k * s, W_dc + (k + 1) * s
+        lg = ens.step(wit[..., a:b].contiguous(), st[..., a:b].contiguous())
+        torch.cuda.synchronize()
+        got[:, k] = lg.cpu().numpy()
+    assert np.isfinite(got).all()
+    want = np.stack([ref.ensemble_logits(dcp, np.stack([data[i][d][0] for d in range(2)]),
+                                         np.stack([data[i][d][1] for d in range(2)]), bbp,
+                                         taps.astype(np.float32), s, W_dc, W_bb, K) for i in pick])
+    assert rel(got[list(pick)], want) <= 2e-2
