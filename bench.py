@@ -676,7 +676,7 @@ def main():
         n_e, s_e = 64, 256
         dc_l1 = gs.DeepClean(torch.from_numpy(synth.deepclean_params(1)).to(dev), layers)
         dc.set_cu_budget(0)  # one stream: nothing runs beside the DeepClean kernels
-        e = ensemble.Ensemble(dc, dc_l1, bb, n_e, W_dc=DC_W, W_bb=BB_W, stride=s_e, precision=prec)
+        e = ensemble.Ensemble(dc, dc_l1, bb, n_e, W_dc=DC_W, W_bb=BB_W, stride=s_e, precision=prec, pipeline=True)
         g = torch.Generator(device="cpu").manual_seed(11)
         e.prefill(torch.randn((2, n_e, DC_C, DC_W), generator=g).to(dev))
         wits = [torch.randn((2, n_e, DC_C, s_e), generator=g).to(dev) for _ in range(8)]
@@ -695,7 +695,7 @@ def main():
         gc.enable()
         gc.unfreeze()
         ms_e = 1e3 * dte / args.steps
-        ens = {"streams": n_e, "stride": s_e, "ms_per_step": ms_e,
+        ens = {"streams": n_e, "stride": s_e, "ms_per_step": ms_e, "pipelined": True,
                "strain_samples_per_s": 2 * n_e * s_e / (ms_e * 1e-3),
                "data_seconds_per_s": n_e * s_e / 4096 / (ms_e * 1e-3),
                "config": f"{n_e} ensemble streams: 2 x (21 x {DC_W}) witness snapshots at 4096 Hz, "

@@ -41,7 +41,7 @@ class Ensemble:
     detectors (same input channels); bbh: a 2-channel BBHnet model."""
 
     def __init__(self, dc_h1, dc_l1, bbh, n, *, W_dc=32768, W_bb=2048, stride=256, taps=None,
-                 precision=gs.BF16, device="cuda:0"):
+                 precision=gs.BF16, device="cuda:0", pipeline=False):
         if stride % 2:
             raise ValueError("the stride must be even (decimation by 2)")
         self.dc = (dc_h1, dc_l1)
@@ -62,10 +62,22 @@ class Ensemble:
         s = stride
         self.wit_off = np.arange(2 * n, dtype=np.int64) * self.C * s
         self.bb_off = np.arange(n, dtype=np.int64) * 2 * (s // 2)
-        self.cleaned = torch.empty((2, n, s), device=self.dev)
+        # pipeline: request k's decimation and BBHnet run on a second stream
+        # while the DeepClean forwards of request k + 1 run on the caller's;
+        # the cleaned-strain and logit buffers alternate between two copies
+        self.pipeline = pipeline
+        nbuf = 2 if pipeline else 1
+        self.cleaned_bufs = [torch.empty((2, n, s), device=self.dev) for _ in range(nbuf)]
+        self.logit_bufs = [torch.empty(n, device=self.dev) for _ in range(nbuf)]
         self.hist = torch.zeros((n, 2, max(K - 1, 1)), device=self.dev)
         self.dec = torch.empty((n, 2, s // 2), device=self.dev)
-        self.logits = torch.empty(n, device=self.dev)
+        self.k = 0
+        if pipeline:
+            self.s_post = torch.cuda.Stream(device=self.dev)
+            self.ev_clean = [torch.cuda.Event() for _ in range(2)]
+            self.ev_post = [torch.cuda.Event() for _ in range(2)]
+            for e in self.ev_post:
+                e.record(torch.cuda.current_stream(self.dev))
         self.ws_dc = torch.empty(dc_h1.workspace_bytes(n, W_dc, precision), dtype=torch.uint8, device=self.dev)
         self.ws_bb = torch.empty(bbh.workspace_bytes(n, W_bb, precision), dtype=torch.uint8, device=self.dev)
 
@@ -80,15 +92,35 @@ class Ensemble:
         """One request of every stream.  witness device [2][n][C][s] (H1
         then L1), strain device [2][n][s] (the s newest strain samples of
         each detector).  Returns the logits tensor [n] (device; overwritten
-        by the next step)."""
+        two steps later, or by the next step without the pipeline).  With the
+        pipeline the logits are written on the ensemble's second stream: wait
+        for ready_event() (or synchronise) before reading them."""
         n, s = self.n, self.s
+        main = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        b = self.k % len(self.cleaned_bufs)
+        cleaned, logits = self.cleaned_bufs[b], self.logit_bufs[b]
+        if self.pipeline:
+            main.wait_event(self.ev_post[b])  # the decimation that read this buffer is done
         self.pool.update(self.slots_h1 + self.slots_l1, [s] * (2 * n), witness.reshape(-1), self.wit_off,
-                         stream=stream)
+                         stream=main)
         for d, slots in enumerate((self.slots_h1, self.slots_l1)):
             self.dc[d].forward(pool=self.pool, slots=slots, W=self.W_dc, strides=[s] * n, strain=strain[d],
-                               clean=self.cleaned[d], precision=self.prec, ws=self.ws_dc, stream=stream)
-        gs.decimate2(x=self.cleaned, taps=self.taps, hist=self.hist, y=self.dec, stream=stream)
-        self.pool.update(self.slots_bb, [s // 2] * n, self.dec.reshape(-1), self.bb_off, stream=stream)
-        self.bbh.forward(pool=self.pool, slots=self.slots_bb, W=self.W_bb, logits=self.logits, precision=self.prec,
-                         ws=self.ws_bb, stream=stream)
-        return self.logits
+                               clean=cleaned[d], precision=self.prec, ws=self.ws_dc, stream=main)
+        post = main
+        if self.pipeline:
+            self.ev_clean[b].record(main)
+            post = self.s_post
+            post.wait_event(self.ev_clean[b])
+        gs.decimate2(x=cleaned, taps=self.taps, hist=self.hist, y=self.dec, stream=post)
+        self.pool.update(self.slots_bb, [s // 2] * n, self.dec.reshape(-1), self.bb_off, stream=post)
+        self.bbh.forward(pool=self.pool, slots=self.slots_bb, W=self.W_bb, logits=logits, precision=self.prec,
+                         ws=self.ws_bb, stream=post)
+        if self.pipeline:
+            self.ev_post[b].record(post)
+        self.k += 1
+        return logits
+
+    def ready_event(self):
+        """With the pipeline: an event recorded after the last step's logits
+        (None without the pipeline: they are ready in stream order)."""
+        return self.ev_post[(self.k - 1) % 2] if self.pipeline and self.k else None

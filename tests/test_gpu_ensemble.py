@@ -121,3 +121,32 @@ def test_ensemble_bench_configuration():
                                          np.stack([data[i][d][1] for d in range(2)]), bbp,
                                          taps.astype(np.float32), s, W_dc, W_bb, K) for i in pick])
     assert rel(got[list(pick)], want) <= 2e-2
+
+
+def test_ensemble_pipeline_bitwise():
+    """With the pipeline (request k's decimation and BBHnet on a second
+    stream while request k + 1's DeepClean forwards run) every request's
+    logits equal those of the sequential schedule bitwise."""
+    n, W_dc, W_bb, s, K = 3, 4096, 2048, 256, 6
+    dcm = [gs.DeepClean(torch.from_numpy(synth.deepclean_params(d)).to(DEV), synth.deepclean_layers())
+           for d in range(2)]
+    bbm = gs.BBHnet(torch.from_numpy(synth.bbhnet_params(0)).to(DEV), synth.bbhnet_stages())
+    U = W_dc + K * s
+    wit = torch.from_numpy(synth.gaussian(91, (2, n, 21, U))).to(DEV)
+    st = torch.from_numpy(synth.gaussian(92, (2, n, U))).to(DEV)
+    res = []
+    for pipe in (False, True):
+        ens = ensemble.Ensemble(dcm[0], dcm[1], bbm, n, W_dc=W_dc, W_bb=W_bb, stride=s, pipeline=pipe)
+        ens.prefill(wit[..., :W_dc].contiguous())
+        out = []
+        for k in range(K):
+            a, b = W_dc + k * s, W_dc + (k + 1) * s
+            lg = ens.step(wit[..., a:b].contiguous(), st[..., a:b].contiguous())
+            out.append(lg.clone() if not pipe else lg)
+            if pipe and k % 2 == 1:        # read the two live buffers before they are reused
+                torch.cuda.synchronize()
+                out[-2], out[-1] = out[-2].clone(), out[-1].clone()
+        torch.cuda.synchronize()
+        res.append(torch.stack(out).cpu())
+    assert torch.isfinite(res[0]).all()
+    assert torch.equal(res[0], res[1])
