@@ -589,3 +589,46 @@ def test_ensemble_wiring_with_silent_deepclean():
         dec = ref.decimate2(strain[:, W_dc:W_dc + (k + 1) * s], taps)
         want = ref.bbhnet_forward(bbp, ref.snapshot_after(dec, dec.shape[-1], W_bb)[None])[0]
         assert abs(got[k] - want) <= 1e-12 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("active", [0, 1])
+def test_ensemble_detector_pairing(active):
+    """Detector d's DeepClean parameters must clean detector d's strain from
+    detector d's witnesses, and the cleaned H1/L1 streams must enter BBHnet as
+    channels 0/1.  One detector gets real parameters and the other all-zero
+    ones (its predicted noise is exactly zero, so its cleaned stream is its
+    raw strain); the expected logits are composed here a different way: all
+    K windows of a detector in one batched forward, the decimation as
+    numpy.convolve then every second sample (pinned equal to decimate2 above),
+    and BBHnet on all K snapshots at once.  Swapping parameters, witnesses or
+    output channels between the detectors fails this."""
+    from paper_2108_12430_amd import synth
+    s, W_dc, W_bb, K = 64, 256, 512, 3
+    p = synth.deepclean_params(0)
+    zero = np.zeros_like(p)
+    dc = [zero, zero]
+    dc[active] = p
+    rng = np.random.default_rng(11 + active)
+    U = W_dc + K * s
+    witness = rng.standard_normal((2, 21, U))
+    strain = rng.standard_normal((2, U))
+    bbp = synth.bbhnet_params(0)
+    taps = ref.lowpass_taps(15, 0.225)
+    got = ref.ensemble_logits(dc, witness, strain, bbp, taps, s, W_dc, W_bb, K)
+
+    cleaned = strain[:, W_dc:].copy()                      # [2][K s]
+    wins = np.stack([witness[active][:, (k + 1) * s:(k + 1) * s + W_dc] for k in range(K)])
+    noise = ref.deepclean_forward(p, wins)                 # [K][W_dc]
+    assert np.max(np.abs(noise[:, -s:])) > 1e-2            # the active detector's noise is not trivial
+    cleaned[active] -= noise[:, -s:].reshape(-1)
+    dec = np.stack([np.convolve(c, taps)[1:K * s:2] for c in cleaned])   # [2][K s / 2]
+    hs = s // 2
+    snaps = np.zeros((K, 2, W_bb))
+    for k in range(K):
+        seg = dec[:, :(k + 1) * hs]
+        snaps[k, :, W_bb - seg.shape[1]:] = seg
+    want = ref.bbhnet_forward(bbp, snaps)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+    # the other pairing gives different logits, so the check above can tell them apart
+    swapped = ref.bbhnet_forward(bbp, snaps[:, ::-1].copy())
+    assert np.max(np.abs(swapped - want)) > 1e-6
