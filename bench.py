@@ -429,6 +429,8 @@ def main():
                          "group's kernels beside it")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--train-only", action="store_true",
+                    help="time only the training step (FP32 and BF16-conv; --steps/--warmup apply), for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -436,6 +438,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.train_only:
+        dev = torch.device("cuda:0")
+        out = {}
+        for prec in ("fp32", "bf16"):
+            out[prec] = train_bench(dev, steps=args.steps, warmup=args.warmup, precision=prec)
+            log(f"bench: training {prec}: {out[prec]['ms_per_step']:.3f} ms/step")
+        print(json.dumps({"training": out}))
+        return
 
     from paper_2108_12430_amd import gwstream as gs
     from paper_2108_12430_amd import synth

@@ -37,8 +37,26 @@ int hip_fail(hipError_t e, const char* what) {
 inline size_t r256(size_t x) { return (x + 255) & ~size_t(255); }
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Ring of pinned host staging slots for the per-call item tables; each slot
-// is reused only after the copy that last read it has completed.
+struct Stager;
+
+// Records a staged table's reuse event when the entry point that staged it
+// returns, i.e. after every launch that reads the table has been enqueued.
+struct StageGuard {
+  Stager* s = nullptr;
+  int k = -1;
+  hipStream_t st = nullptr;
+  StageGuard() = default;
+  StageGuard(const StageGuard&) = delete;
+  StageGuard& operator=(const StageGuard&) = delete;
+  inline ~StageGuard();
+};
+
+// Ring of pinned host staging slots for the per-call item tables.  Slot k's
+// event is recorded on the caller's stream after the last launch of the call
+// that staged it, so a later call (on any stream) reuses the slot only after
+// the kernels that read its table have finished.  gen[k] counts the uses of
+// slot k: a (k, gen) pair names one call's completion event until the slot
+// is staged again, by which time the host has waited for that event.
 struct Stager {
   static constexpr int K = 32;
   Item* host = nullptr;
@@ -47,6 +65,7 @@ struct Stager {
   int next = 0;
   hipEvent_t ev[K] = {};
   bool used[K] = {};
+  uint64_t gen[K] = {};
   static size_t dev_bytes(int cap) { return r256(sizeof(Item) * (size_t)cap * K); }
   int init(void* dev_region, int cap_items) {
     cap = cap_items;
@@ -66,20 +85,35 @@ struct Stager {
     if (host) (void)hipHostFree(host);
     host = nullptr;
   }
-  int stage(const std::vector<Item>& items, hipStream_t st, const Item** out) {
+  // True while call (k, g) may still have work in flight.
+  bool pending(int k, uint64_t g) const {
+    return k >= 0 && gen[k] == g && hipEventQuery(ev[k]) == hipErrorNotReady;
+  }
+  int stage(const std::vector<Item>& items, hipStream_t st, const Item** out, StageGuard* guard) {
     if ((int)items.size() > cap) return fail(GW_EINVAL, "too many items in one call");
     const int k = next;
     next = (next + 1) % K;
     if (used[k]) HIPCHK(hipEventSynchronize(ev[k]));
+    ++gen[k];
     std::memcpy(host + (size_t)k * cap, items.data(), items.size() * sizeof(Item));
     HIPCHK(hipMemcpyAsync(dev + (size_t)k * cap, host + (size_t)k * cap, items.size() * sizeof(Item),
                           hipMemcpyHostToDevice, st));
+    // provisional record (covers the copy if the call ends before its launches);
+    // the guard records again after the launches
     HIPCHK(hipEventRecord(ev[k], st));
     used[k] = true;
+    guard->s = this;
+    guard->k = k;
+    guard->st = st;
     *out = dev + (size_t)k * cap;
     return GW_OK;
   }
+  void done(int k, hipStream_t st) { (void)hipEventRecord(ev[k], st); }
 };
+
+StageGuard::~StageGuard() {
+  if (s && k >= 0) s->done(k, st);
+}
 
 // Optional per-launch timing with HIP events recorded on the launch stream.
 struct Prof {
@@ -172,10 +206,54 @@ struct gw_pool {
     size_t off = 0, size = 0;
     int head = 0;
     int64_t n_seen = 0;
+    hipEvent_t fill = nullptr;  // recorded after the zero-fill of gw_stream_open
+    int last_k = -1;            // the last call that read or wrote the ring: stager
+    uint64_t last_gen = 0;      // slot and generation (see Stager)
+  };
+  // A closed slot's region whose last users may still be running: a later
+  // open that reuses any of its bytes orders its zero-fill after them.
+  struct Retired {
+    size_t off, size;
+    hipEvent_t fill;
+    int k;
+    uint64_t gen;
   };
   std::vector<Slot> slots;
   std::map<size_t, size_t> free_;  // offset -> size
+  std::vector<Retired> retired;
+  std::vector<hipEvent_t> spare_ev;
   size_t used = 0;
+
+  hipEvent_t get_event() {
+    if (!spare_ev.empty()) {
+      hipEvent_t e = spare_ev.back();
+      spare_ev.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+  // Drop retired regions whose users have all finished.
+  void prune() {
+    size_t j = 0;
+    for (size_t i = 0; i < retired.size(); ++i) {
+      Retired& r = retired[i];
+      const bool busy = (r.fill && hipEventQuery(r.fill) == hipErrorNotReady) || stager.pending(r.k, r.gen);
+      if (busy) {
+        retired[j++] = r;
+      } else if (r.fill) {
+        spare_ev.push_back(r.fill);
+      }
+    }
+    retired.resize(j);
+  }
+  void mark_used(const int32_t* ids, int n, const StageGuard& g) {
+    for (int i = 0; i < n; ++i) {
+      slots[ids[i]].last_k = g.k;
+      slots[ids[i]].last_gen = stager.gen[g.k];
+    }
+  }
 
   static size_t ring_bytes(int C, int W) { return r256((size_t)C * W * 4) + r256((size_t)C * W * 2); }
   int64_t ring_elem(const Slot& s) const { return (int64_t)(s.off / 4); }
@@ -251,6 +329,14 @@ extern "C" int gw_pool_init(void* dev_arena, size_t bytes, int32_t max_slots, in
 extern "C" int gw_pool_free(gw_pool* pool) {
   if (!pool) return fail(GW_EINVAL, "null pool");
   pool->stager.release();
+  for (auto& r : pool->retired)
+    if (r.fill) pool->spare_ev.push_back(r.fill);
+  for (auto& sl : pool->slots)
+    if (sl.fill) pool->spare_ev.push_back(sl.fill);
+  for (hipEvent_t e : pool->spare_ev) {
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
+  }
   delete pool;
   return GW_OK;
 }
@@ -266,11 +352,28 @@ extern "C" int gw_stream_open(gw_pool* pool, int32_t C, int32_t W, void* hip_str
     }
   if (id < 0) return fail(GW_ENOMEM, "slot table full");
   const size_t size = gw_pool::ring_bytes(C, W);
+  hipEvent_t fill = pool->get_event();
+  if (!fill) return fail(GW_EHIP, "hipEventCreate failed");
   size_t off = 0;
-  if (!pool->alloc(size, &off)) return fail(GW_ENOMEM, "arena full");
-  hipError_t e = gw::launch_fill_zero(pool->arena + off, size, S(hip_stream));
+  if (!pool->alloc(size, &off)) {
+    pool->spare_ev.push_back(fill);
+    return fail(GW_ENOMEM, "arena full");
+  }
+  const hipStream_t st = S(hip_stream);
+  // the region may still be read or written by work of a closed slot
+  // (possibly on another stream): the zero-fill waits for it
+  pool->prune();
+  hipError_t e = hipSuccess;
+  for (const auto& r : pool->retired) {
+    if (r.off >= off + size || off >= r.off + r.size) continue;
+    if (e == hipSuccess && r.fill) e = hipStreamWaitEvent(st, r.fill, 0);
+    if (e == hipSuccess && pool->stager.pending(r.k, r.gen)) e = hipStreamWaitEvent(st, pool->stager.ev[r.k], 0);
+  }
+  if (e == hipSuccess) e = gw::launch_fill_zero(pool->arena + off, size, st);
+  if (e == hipSuccess) e = hipEventRecord(fill, st);
   if (e != hipSuccess) {
     pool->release(off, size);
+    pool->spare_ev.push_back(fill);
     return hip_fail(e, "fill_zero");
   }
   auto& s = pool->slots[id];
@@ -281,6 +384,9 @@ extern "C" int gw_stream_open(gw_pool* pool, int32_t C, int32_t W, void* hip_str
   s.size = size;
   s.head = 0;
   s.n_seen = 0;
+  s.fill = fill;
+  s.last_k = -1;
+  s.last_gen = 0;
   *slot = id;
   return GW_OK;
 }
@@ -289,8 +395,10 @@ extern "C" int gw_stream_close(gw_pool* pool, int32_t slot) {
   if (!pool) return fail(GW_EINVAL, "null pool");
   CHK(pool->check_slot(slot));
   auto& s = pool->slots[slot];
+  pool->retired.push_back({s.off, s.size, s.fill, s.last_k, s.last_gen});
   pool->release(s.off, s.size);
   s = gw_pool::Slot();
+  pool->prune();
   return GW_OK;
 }
 
@@ -319,7 +427,9 @@ extern "C" int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_
   items[0].C = s.C;
   items[0].W = s.W;
   const Item* dev = nullptr;
-  CHK(pool->stager.stage(items, S(hip_stream), &dev));
+  StageGuard guard;
+  CHK(pool->stager.stage(items, S(hip_stream), &dev, &guard));
+  pool->mark_used(&slot, 1, guard);
   LAUNCH("gather", S(hip_stream), gw::launch_gather(pool->arena, dev, 1, s.C, s.W, out, out_bf16, S(hip_stream)));
   return GW_OK;
 }
@@ -361,7 +471,9 @@ extern "C" int snapshot_update(gw_pool* pool, int32_t n, const int32_t* slots, c
     max_cs = std::max(max_cs, s.C * strides[i]);
   }
   const Item* dev = nullptr;
-  CHK(pool->stager.stage(items, S(hip_stream), &dev));
+  StageGuard guard;
+  CHK(pool->stager.stage(items, S(hip_stream), &dev, &guard));
+  pool->mark_used(slots, n, guard);
   LAUNCH("snapshot", S(hip_stream), gw::launch_snapshot(pool->arena, dev, n, max_cs, samples, S(hip_stream)));
   for (int i = 0; i < n; ++i) {
     auto& s = pool->slots[slots[i]];
@@ -917,11 +1029,14 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
     }
   }
   const Item* dev_items = nullptr;
+  StageGuard guard;
   if (need_items) {
-    if (pool)
-      CHK(pool->stager.stage(items, st, &dev_items));
-    else
-      CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items));
+    if (pool) {
+      CHK(pool->stager.stage(items, st, &dev_items, &guard));
+      pool->mark_used(slots, n, guard);
+    } else {
+      CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items, &guard));
+    }
   }
 
   char* wsb = reinterpret_cast<char*>(ws);
@@ -1130,7 +1245,8 @@ extern "C" int deepclean_overlap_average(const gw_model* m, int32_t n, int32_t W
     max_s = std::max(max_s, s);
   }
   const Item* dev_items = nullptr;
-  CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items));
+  StageGuard guard;
+  CHK(const_cast<gw_model*>(m)->stager.stage(items, st, &dev_items, &guard));
   LAUNCH("overlap_average", st,
          gw::launch_overlap_average(dev_items, n, max_s, W, depth, noise, state, strain, clean, avg, st));
   return GW_OK;
@@ -1373,6 +1489,8 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GW_EINVAL, "workspace not 256-byte aligned");
   char* wsb = reinterpret_cast<char*>(ws);
   const float* in = x;
+  StageGuard guard;  // the gathered window is read by the first stage only, but
+                     // the table stays reserved until the call's last launch
   if (pool) {
     std::vector<Item> items(n);
     std::vector<char> seen(pool->max_slots, 0);
@@ -1390,7 +1508,8 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
       items[i].W = s.W;
     }
     const Item* dev = nullptr;
-    CHK(pool->stager.stage(items, st, &dev));
+    CHK(pool->stager.stage(items, st, &dev, &guard));
+    pool->mark_used(slots, n, guard);
     float* g = reinterpret_cast<float*>(wsb + b.gath);
     LAUNCH("gather", st, gw::launch_gather(pool->arena, dev, n, m->c_in, W, g, nullptr, st));
     in = g;
