@@ -319,6 +319,21 @@ int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float f_hi, cons
                     const float* noise, float* loss, float* dnoise, void* ws, size_t ws_bytes,
                     void* hip_stream);
 
+/*
+ * gw_bandpass_mse_noalloc: gw_bandpass_mse for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * gw_bandpass_mse (the same kernels, so bitwise the same outputs) without the
+ * workspace: the projection scratch is a library-owned static device array of
+ * 1 MiB per GPU, held until the process ends, so n x (number of band bins)
+ * must not exceed 131072 (else GW_EINVAL, nothing enqueued).  The call
+ * allocates nothing; the first call on a device looks up that device's copy
+ * of the array.  Calls that overlap on one GPU (concurrent streams, or
+ * threads) share that array and race: serialise them.
+ */
+int gw_bandpass_mse_noalloc(int32_t n, int32_t W, float fs, float f_lo, float f_hi, const float* strain,
+                            const float* noise, float* loss, float* dnoise, void* hip_stream);
+
 /* ---- BBHnet ---------------------------------------------------------- */
 /*
  * bbhnet_forward: one logit (event likelihood score) per window.

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1417,6 +1418,65 @@ extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float
   CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
   if (ws_bytes < (size_t)n * (hi - lo + 1) * 2 * sizeof(float)) return fail(GW_EINVAL, "workspace too small");
   LAUNCH("bandpass", S(hip_stream), gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ws), loss, dnoise,
+                             S(hip_stream)));
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Band-passed MSE without allocation.  The projection scratch of
+// gw_bandpass_mse (n x bins (cos, sin) pairs) lives in a file-scope device
+// array: every GPU the library runs on holds one copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory, so
+// the kernels get the address that hipGetSymbolAddress returns for the
+// stream's device (looked up once per device, with that device current).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // per device ordinal; null until looked up
+
+int scratch_for_stream(hipStream_t st, void** out) {
+  int dev = -1;
+  if (st)
+    HIPCHK(hipStreamGetDevice(st, &dev));
+  else
+    HIPCHK(hipGetDevice(&dev));  // the null stream runs on the current device
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(GW_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return GW_OK;
+}
+}  // namespace
+
+extern "C" int gw_bandpass_mse_noalloc(int32_t n, int32_t W, float fs, float f_lo, float f_hi,
+                                       const float* strain, const float* noise, float* loss, float* dnoise,
+                                       void* hip_stream) {
+  if (n < 1 || !strain || !noise || (!loss && !dnoise)) return fail(GW_EINVAL, "bad argument");
+  int lo, hi;
+  CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
+  const size_t need = (size_t)n * (hi - lo + 1) * 2 * sizeof(float);
+  if (need > kNoAllocScratchBytes)
+    return fail(GW_EINVAL, "n x band bins = " + std::to_string((size_t)n * (hi - lo + 1)) +
+                               " exceeds the no-allocation scratch limit of " +
+                               std::to_string(kNoAllocScratchBytes / (2 * sizeof(float))));
+  void* ptr = nullptr;
+  CHK(scratch_for_stream(S(hip_stream), &ptr));
+  // every (window, bin) pair the loss and gradient read is written first by
+  // this call's projection kernel, so nothing in the array needs clearing
+  HIPCHK(gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ptr), loss, dnoise,
                              S(hip_stream)));
   return GW_OK;
 }

@@ -30,7 +30,7 @@ EXPORTS = [
     "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
     "deepclean_backward_scratch",
     "deepclean_backward",
-    "gw_bandpass_workspace", "gw_bandpass_mse", "bbhnet_workspace", "bbhnet_forward",
+    "gw_bandpass_workspace", "gw_bandpass_mse", "gw_bandpass_mse_noalloc", "bbhnet_workspace", "bbhnet_forward",
     "gw_profile_begin", "gw_profile_end",
 ]
 
@@ -78,6 +78,7 @@ def lib():
             "deepclean_backward": ([vp, i32, i32, vp, vp, vp, vp, u32, i32, vp, sz, vp], C.c_int),
             "gw_bandpass_workspace": ([i32, i32, f32, f32, f32, P(sz)], C.c_int),
             "gw_bandpass_mse": ([i32, i32, f32, f32, f32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
+            "gw_bandpass_mse_noalloc": ([i32, i32, f32, f32, f32, vp, vp, vp, vp, vp], C.c_int),
             "bbhnet_workspace": ([vp, i32, i32, i32, P(sz)], C.c_int),
             "bbhnet_forward": ([vp, vp, vp, vp, i32, i32, vp, i32, vp, sz, vp], C.c_int),
             "gw_profile_begin": ([], C.c_int),
@@ -378,6 +379,15 @@ def bandpass_mse(strain, noise, fs=4096.0, f_lo=55.0, f_hi=65.0, want_grad=True,
     check(lib().gw_bandpass_mse(n, W, fs, f_lo, f_hi, _ptr(_f32(strain, "strain")), _ptr(_f32(noise, "noise")),
                                 _ptr(loss), _ptr(dn), _ptr(ws), ws.numel(), _stream(stream)))
     return loss, dn
+
+
+def bandpass_mse_noalloc(strain, noise, loss, dnoise=None, fs=4096.0, f_lo=55.0, f_hi=65.0, stream=None):
+    """gw_bandpass_mse_noalloc: writes the loss into `loss` ([1] float32) and
+    the gradient into `dnoise` (or skips it when None); allocates nothing."""
+    n, W = strain.shape
+    check(lib().gw_bandpass_mse_noalloc(n, W, fs, f_lo, f_hi, _ptr(_f32(strain, "strain")),
+                                        _ptr(_f32(noise, "noise")), _ptr(_f32(loss, "loss")),
+                                        _ptr(None if dnoise is None else _f32(dnoise, "dnoise")), _stream(stream)))
 
 
 def decimate2(*, x, taps, hist, y, stream=None):
