@@ -494,6 +494,7 @@ struct LayerD {
   int64_t w, b, g, be, m, v;  // parameter offsets (floats)
   size_t scale, shift;        // packed byte offsets
   size_t wbf;                 // packed bf16 weights byte offset
+  size_t wbf_lo;              // packed low bf16 terms (training variant's split operands)
   size_t wf16;                // packed fp16 weights byte offset (fused-shape networks)
   bool bf16;                  // BF16 kernel available
 };
@@ -579,8 +580,11 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
     for (auto& ly : m.layers) {
       ly.bf16 = gw::conv_bf16_supported(ly.ci, ly.co, ly.k, ly.s, ly.type == GW_LAYER_CONVT);
       if (ly.bf16) {
+        const size_t eb = r256(2 * gw::conv_bf16_packed_elems(ly.ci, ly.co, ly.k, ly.type == GW_LAYER_CONVT));
         ly.wbf = pk;
-        pk += r256(2 * gw::conv_bf16_packed_elems(ly.ci, ly.co, ly.k, ly.type == GW_LAYER_CONVT));
+        pk += eb;
+        ly.wbf_lo = pk;
+        pk += eb;
       }
       m.bf16_all = m.bf16_all && ly.bf16;
     }
@@ -668,12 +672,15 @@ int pack_model(gw_model* m, hipStream_t st) {
       HIPCHK(gw::launch_fold_bn(P + ly.b, ly.bn ? P + ly.g : nullptr, ly.bn ? P + ly.be : nullptr,
                                 ly.bn ? P + ly.m : nullptr, ly.bn ? P + ly.v : nullptr, sc, sh, ly.co,
                                 st));
-      if (ly.bf16)
+      if (ly.bf16) {
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf), ly.ci,
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st));
+        HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf_lo), ly.ci,
+                                    ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, gw::PACK_BF16_LO));
+      }
       if (m->fused)
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wf16), ly.ci,
-                                    ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, true));
+                                    ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, gw::PACK_F16));
     }
   } else {
     for (auto& sd : m->stages) {
@@ -1103,6 +1110,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
     gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
     p.items = dev_items;
     p.x = in;
+    if (precision == GW_BF16) p.wpk_lo = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf_lo);
     if (l == L - 1) {
       p.noise = noise;
       p.clean = clean;
@@ -1309,6 +1317,7 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
       const LayerD& ly = m->layers[l];
       gw::ConvP p = conv_params(m, ly, n, lin[l], lout[l]);
       p.x = in;
+      if (precision == GW_BF16) p.wpk_lo = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf_lo);
       float* a = scf(b.a[l]);
       float* z = ly.bn ? scf(b.z[l]) : a;
       p.y = z;

@@ -37,7 +37,12 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-enum InFmt { IN_F32 = 0, IN_BF16 = 1, IN_RING = 2, IN_RING_F32 = 3 };  // IN_RING_F32: fused FP16 kernel only
+// IN_RING_F32: fused FP16 kernel only.  IN_F32S: FP32 input split into two
+// BF16 terms, x = hi + lo (hi = RNE(x), lo = RNE(x - hi)), staged as two
+// tiles; with the weights split the same way each product takes three MFMAs
+// (hi*hi + lo_w*hi_x + hi_w*lo_x), which leaves a relative error of about
+// 2^-16 per product instead of 2^-8 (the training variant's convolutions).
+enum InFmt { IN_F32 = 0, IN_BF16 = 1, IN_RING = 2, IN_RING_F32 = 3, IN_F32S = 4 };
 
 // Geometry of the polyphase/strided column view of a layer (host + device).
 struct Geo {
@@ -83,7 +88,7 @@ static inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
 
 __global__ void pack_bf16_kernel(const float* w, uint16_t* out, int Ci, int Co, int k, int s, int p,
                                  bool tr, int nph, int kt, int padc, int MT, int KS, int CIP,
-                                 int total, bool f16) {
+                                 int total, int mode) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
   const int e = idx & 7;
@@ -106,7 +111,12 @@ __global__ void pack_bf16_kernel(const float* w, uint16_t* out, int Ci, int Co, 
       if (j >= 0 && j < k) v = w[((int64_t)i * Co + o) * k + j];
     }
   }
-  out[idx] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)v) : bf16_rne(v);
+  if (mode == PACK_F16) {
+    out[idx] = __builtin_bit_cast(uint16_t, (_Float16)v);
+  } else {
+    const uint16_t hi = bf16_rne(v);
+    out[idx] = mode == PACK_BF16_LO ? bf16_rne(v - bf16_to_f(hi)) : hi;
+  }
 }
 
 static void frag_dims(int Ci, int Co, int k, int s, int p, bool tr, int* MT, int* KS, int* CIP,
@@ -126,14 +136,14 @@ size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool tr) {
 }
 
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool tr,
-                            hipStream_t st, bool f16) {
+                            hipStream_t st, int mode) {
   const int s = tr ? 2 : 1, p = 3;
   int MT, KS, CIP;
   Geo g;
   frag_dims(Ci, Co, k, s, p, tr, &MT, &KS, &CIP, &g);
   const int total = g.nph * MT * KS * 512;
   hipLaunchKernelGGL(pack_bf16_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, Ci, Co, k, s,
-                     p, tr, g.nph, g.kt, g.padc, MT, KS, CIP, total, f16);
+                     p, tr, g.nph, g.kt, g.padc, MT, KS, CIP, total, mode);
   return hipGetLastError();
 }
 
@@ -149,9 +159,10 @@ template <int CIP, int ROWS, int IN, int NTHR = 256>
 struct InRaw {
   static constexpr int NCHMAX = (ROWS + 7 + 7) / 8;             // 8-position chunks per channel
   static constexpr int ITEMS = (NCHMAX * CIP + NTHR - 1) / NTHR;  // (channel, chunk) items per thread
-  static constexpr int NV = IN == IN_F32 ? 2 : 1;
+  static constexpr int NV = (IN == IN_F32 || IN == IN_F32S) ? 2 : 1;
+  static_assert(ITEMS <= 32, "one mask bit per item");
   uint4 v[ITEMS][NV];  // raw 16-byte pieces (two for FP32 input)
-  uint32_t f32mask;    // items whose v[it][0..1] still hold 8 FP32 values
+  uint32_t f32mask;    // items whose v[it][0..1] still hold 8 FP32 values (always, for IN_F32S)
 };
 
 // Issue the global loads of one tile's input window into registers.  Tile
@@ -190,9 +201,14 @@ __device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN, NTHR>& R, const 
     const int i = e % CIP, ch = e / CIP;
     const int qc = qa + 8 * ch;
     R.v[it][0] = make_uint4(0, 0, 0, 0);
+    if (IN == IN_F32S) {
+      // split staging keeps every item in FP32 (zeros outside the signal)
+      R.v[it][R.NV - 1] = make_uint4(0, 0, 0, 0);
+      R.f32mask |= 1u << it;
+    }
     if (ch < nch && i < Ci) {
       if (vec && qc >= 0 && qc + 8 <= Lin) {
-        if (IN == IN_F32) {
+        if (IN == IN_F32 || IN == IN_F32S) {
           const uint4* src = reinterpret_cast<const uint4*>(fbase + (int64_t)i * ld + qc);
           R.v[it][0] = src[0];
           R.v[it][R.NV - 1] = src[1];
@@ -205,6 +221,17 @@ __device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN, NTHR>& R, const 
           }
           R.v[it][0] = *reinterpret_cast<const uint4*>(hbase + (int64_t)i * ld + ph);
         }
+      } else if (IN == IN_F32S) {
+        float f[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = qc + k;
+          f[k] = (q >= 0 && q < Lin) ? fbase[(int64_t)i * ld + q] : 0.0f;
+        }
+        R.v[it][0] = make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                                __float_as_uint(f[3]));
+        R.v[it][R.NV - 1] = make_uint4(__float_as_uint(f[4]), __float_as_uint(f[5]), __float_as_uint(f[6]),
+                                       __float_as_uint(f[7]));
       } else {
         uint16_t v[8];
 #pragma unroll
@@ -235,8 +262,10 @@ __device__ __forceinline__ void load_input(InRaw<CIP, ROWS, IN, NTHR>& R, const 
 // row used by padded K entries.
 // HALF > 0 stores row r at (r & 1) * HALF + (r >> 1): even rows first, then
 // odd rows, so a stride-2 reader walks consecutive LDS rows.
+// IN_F32S writes the high BF16 terms to `tile` and the low terms to `tile_lo`.
 template <int CIP, int ROWS, int RS, int IN, int NTHR = 256, int HALF = 0>
-__device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROWS, IN, NTHR>& R, int q0) {
+__device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROWS, IN, NTHR>& R, int q0,
+                                            uint16_t* tile_lo = nullptr) {
   constexpr int ITEMS = InRaw<CIP, ROWS, IN, NTHR>::ITEMS;
   const int qa = q0 - (((q0 % 8) + 8) % 8);
   const int nch = (q0 + ROWS - qa + 7) / 8;
@@ -245,8 +274,17 @@ __device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROW
     const int e = threadIdx.x + NTHR * it;
     const int i = e % CIP, ch = e / CIP;
     if (ch >= nch) continue;
-    uint16_t v[8];
-    if (IN == IN_F32 && (R.f32mask & (1u << it))) {
+    uint16_t v[8], vl[8];
+    if (IN == IN_F32S) {
+      const uint4 a = R.v[it][0], c = R.v[it][R.NV - 1];
+      const float f[8] = {__uint_as_float(a.x), __uint_as_float(a.y), __uint_as_float(a.z), __uint_as_float(a.w),
+                          __uint_as_float(c.x), __uint_as_float(c.y), __uint_as_float(c.z), __uint_as_float(c.w)};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v[k] = bf16_rne(f[k]);
+        vl[k] = bf16_rne(f[k] - bf16_to_f(v[k]));  // exact difference, rounded
+      }
+    } else if (IN == IN_F32 && (R.f32mask & (1u << it))) {
       const uint4 a = R.v[it][0], c = R.v[it][R.NV - 1];
       v[0] = bf16_rne(__uint_as_float(a.x)); v[1] = bf16_rne(__uint_as_float(a.y));
       v[2] = bf16_rne(__uint_as_float(a.z)); v[3] = bf16_rne(__uint_as_float(a.w));
@@ -262,11 +300,17 @@ __device__ __forceinline__ void store_input(uint16_t* tile, const InRaw<CIP, ROW
     for (int k = 0; k < 8; ++k) {
       const int r = r0 + k;
       const int pr = HALF ? (r & 1) * HALF + (r >> 1) : r;
-      if (r >= 0 && r < ROWS) tile[pr * RS + i] = v[k];
+      if (r >= 0 && r < ROWS) {
+        tile[pr * RS + i] = v[k];
+        if (IN == IN_F32S) tile_lo[pr * RS + i] = vl[k];
+      }
     }
   }
   constexpr int PZ = HALF ? (ROWS & 1) * HALF + (ROWS >> 1) : ROWS;
-  for (int e = threadIdx.x; e < RS; e += NTHR) tile[PZ * RS + e] = 0;
+  for (int e = threadIdx.x; e < RS; e += NTHR) {
+    tile[PZ * RS + e] = 0;
+    if (IN == IN_F32S) tile_lo[PZ * RS + e] = 0;
+  }
 }
 
 // Shortcut tile for the residual stage: row c holds the stage input at
@@ -372,12 +416,16 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   constexpr bool OTILE = EPI != EPI_OUT && EPI != EPI_RESID_GAP && !OUT_F32;
   // the input tile's LDS is reused for the BF16 output tile [C_out][NPH*TN]
   constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * TNO ? (ROWS + 1) * RS : 16 * MTB * TNO;
+  // split operands (IN_F32S): a second tile of low terms, weights read per wave
+  constexpr bool SPL = IN == IN_F32S;
+  static_assert(!SPL || (AM == 0 && CSP == 0 && OUT_F32), "split operands: FP32-output layers, AM = 0");
   // weights staged in LDS once per block when they fit beside the tile; only
   // then is the next tile prefetched (LDS reads do not wait on global loads)
-  constexpr bool ALDS = AM == 0 && 2 * TILE + NFRAG * 1024 <= 80 * 1024;
+  constexpr bool ALDS = AM == 0 && !SPL && 2 * TILE + NFRAG * 1024 <= 80 * 1024;
   constexpr int ACH = AM ? NPH * MTB * 64 : 1;  // 16-byte pieces of one K step's fragments
   constexpr int APT = (ACH + 255) / 256;        // pieces per thread
   __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
+  __shared__ __attribute__((aligned(16))) uint16_t tile_lo[SPL ? (ROWS + 1) * RS : 8];
   __shared__ __attribute__((aligned(16))) uint16_t xt[CSP > 0 ? (TN + 1) * RSX : 8];
   __shared__ __attribute__((aligned(16))) uint4 alds[ALDS ? NFRAG * 64 : 1];
   __shared__ __attribute__((aligned(16))) uint4 achunk[2 * ACH];
@@ -395,6 +443,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lg = lane >> 4;
   const uint4* wp = reinterpret_cast<const uint4*>(p.wpk);
+  const uint4* wpl = reinterpret_cast<const uint4*>(p.wpk_lo);
 
   if (ALDS)
     for (int e = threadIdx.x; e < (ALDS ? NFRAG * 64 : 0); e += 256) {
@@ -427,7 +476,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
   for (int t = bi; t < total; t += tstep) {
     const int b = t / tiles_per;
     const int col0 = (t % tiles_per) * TN;
-    store_input<CIP, ROWS, RS, IN>(tile, raw, SC * col0 - padc);
+    store_input<CIP, ROWS, RS, IN>(tile, raw, SC * col0 - padc, tile_lo);
     if (CSP > 0) store_shortcut<CSP, TN, RSX>(xt, sraw);
     if constexpr (AM == 1) {
       // K step 0's fragments into buffer 0 (piece e = fragment (e >> 6), lane e & 63)
@@ -512,25 +561,37 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvP p, int padc, int ncol) {
     for (int ks = 0; ks < (AM == 1 ? 0 : KS); ++ks) {
       const int kappa = 32 * ks + 8 * lg;
       const int jj = kappa / CIP, i0 = kappa - jj * CIP;
-      uint4 af[NPH][MTB];
+      uint4 af[NPH][MTB], afl[SPL ? NPH : 1][SPL ? MTB : 1];
 #pragma unroll
       for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-        for (int mt = 0; mt < MTB; ++mt)
+        for (int mt = 0; mt < MTB; ++mt) {
           af[ph][mt] = ALDS ? alds[ALDS ? ((ph * MTB + mt) * KS + ks) * 64 + lane : 0]
                             : wp[((ph * MT + ms * MTB + mt) * KS + ks) * 64 + lane];
+          if constexpr (SPL) afl[ph][mt] = wpl[((ph * MT + ms * MTB + mt) * KS + ks) * 64 + lane];
+        }
 #pragma unroll
       for (int nt = 0; nt < NTW; ++nt) {
         const int c = (wave * NTW + nt) * 16 + lc;
         const int row = (jj < KT) ? SC * c + jj : ROWS;
         const uint4 bv = *reinterpret_cast<const uint4*>(&tile[row * RS + i0]);
         const bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
+        bf16x8 bl = bb;
+        if constexpr (SPL) bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&tile_lo[row * RS + i0]));
 #pragma unroll
         for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
-          for (int mt = 0; mt < MTB; ++mt)
+          for (int mt = 0; mt < MTB; ++mt) {
+            if constexpr (SPL) {
+              // small terms first: lo_w * hi_x + hi_w * lo_x, then hi_w * hi_x
+              acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, afl[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
+              acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, af[ph][mt]), bl, acc[nt][ph][mt], 0, 0, 0);
+            }
             acc[nt][ph][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                 __builtin_bit_cast(bf16x8, af[ph][mt]), bb, acc[nt][ph][mt], 0, 0, 0);
+          }
       }
     }
     if (CSP > 0) {
@@ -659,7 +720,7 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   // same test as the kernel's ALDS: persistent grid only when weights fit in LDS
   constexpr int ROWS = SC * (TN - 1) + KT, RS = CIP + 8, KS = (KT * CIP + 31) / 32;
   constexpr int TILE = (ROWS + 1) * RS > 16 * MTB * NPH * TN ? (ROWS + 1) * RS : 16 * MTB * NPH * TN;
-  constexpr bool ALDS = AM == 0 && 2 * TILE + NPH * MTB * KS * 1024 <= 80 * 1024;
+  constexpr bool ALDS = AM == 0 && IN != IN_F32S && 2 * TILE + NPH * MTB * KS * 1024 <= 80 * 1024;
   auto kern = conv_mfma<CIP, MT, NPH, KT, SC, NTW, EPI, IN, OUT_F32, XS_F32, CSP, MS, AM>;
   const int64_t tiles = (int64_t)((g.ncol + TN - 1) / TN) * p.n;
   if (tiles * MS > (int64_t)1 << 30) return hipErrorInvalidValue;
@@ -724,17 +785,21 @@ static hipError_t launch_t(const ConvP& p, const Geo& g, hipStream_t st) {
   X(64, 8, 1, 7, 2, EPI_RELU, IN_BF16, false, false, 0, 2, 2, 1)               \
   X(128, 8, 1, 7, 1, EPI_RESID_RELU, IN_BF16, true, false, 64, 2, 1, 1)        \
   X(128, 8, 1, 7, 1, EPI_RESID_GAP, IN_BF16, true, false, 64, 2, 1, 1)         \
-  /* training forward (BF16 conv variant): FP32 activations in, FP32 z out */      \
-  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                    \
-  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                   \
-  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32, true, false, 0, 4, 1, 0)                    \
+  /* FP32-input output conv (a network whose last layer reads FP32) */            \
   X(8, 1, 1, 7, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                     \
-  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                    
+  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32, true, false, 0, 4, 1, 0)                     \
+  /* training forward (BF16 conv variant): FP32 activations in, split into      \
+     hi + lo BF16 terms (three MFMAs per product), FP32 z out */                   \
+  X(24, 1, 1, 7, 2, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(8, 1, 1, 7, 2, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                   \
+  X(16, 2, 1, 7, 2, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(32, 4, 1, 7, 2, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(64, 2, 2, 4, 1, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(32, 1, 2, 4, 1, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(16, 1, 2, 4, 1, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                  \
+  X(8, 1, 2, 4, 1, EPI_BIAS, IN_F32S, true, false, 0, 2, 1, 0)                   \
+  X(8, 1, 1, 7, 1, EPI_OUT, IN_F32S, true, false, 0, 2, 1, 0)                    \
+  X(8, 1, 2, 4, 1, EPI_OUT, IN_F32S, true, false, 0, 2, 1, 0)                   
 
 // Large layers take the AM = 1 variants where they exist: at least ~4 blocks
 // of 128 columns per CU, or, for layers with C_in x C_out >= 4096, at least
@@ -772,7 +837,8 @@ bool conv_bf16_supported(int Ci, int Co, int k, int stride, bool tr) {
 }
 
 // The ABI passes: input format through p.x (fp32), p.xh (bf16) or ring
-// (src == SRC_RING); output fp32 when p.y is set and p.yh is not; residual
+// (src == SRC_RING), FP32 input split into hi + lo terms when p.wpk_lo (the
+// low weight terms) is set; output fp32 when p.y is set and p.yh is not; residual
 // shortcut input through p.xs (fp32) or p.xsh (bf16) with weights p.wspk.
 hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream_t st) {
   if (p.k != 7 || p.pad != 3) return hipErrorNotSupported;
@@ -784,7 +850,7 @@ hipError_t launch_conv_bf16(const ConvP& p, bool tr, int epi, int src, hipStream
   k.kt = g.kt;
   k.sc = g.sc;
   k.epi = epi;
-  k.in = src == SRC_RING ? IN_RING : (p.xh ? IN_BF16 : IN_F32);
+  k.in = src == SRC_RING ? IN_RING : (p.xh ? IN_BF16 : (p.wpk_lo ? IN_F32S : IN_F32));
   k.out_f32 = (epi == EPI_OUT || p.yh == nullptr) ? 1 : 0;
   const bool res = epi == EPI_RESID_RELU || epi == EPI_RESID_GAP;
   if (epi == EPI_RESID_GAP) k.out_f32 = 1;

@@ -48,6 +48,7 @@ struct ConvP {
   const float* w;
   int64_t wso, wsi;
   const uint16_t* wpk;     // packed bf16 weights (BF16 kernels)
+  const uint16_t* wpk_lo;  // low bf16 terms of the weights (split FP32 input), or null
   const uint16_t* wspk;    // packed bf16 1x1 shortcut weights (BF16 residual epilogue)
   const float* bias;
   const float* scale;
@@ -86,9 +87,11 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
                                 const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
                                 bool f16 = false);
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
-// f16: IEEE half (round to nearest even) instead of bf16
+// mode PACK_BF16: bf16 (RNE); PACK_F16: IEEE half (RNE); PACK_BF16_LO: the
+// bf16 rounding of w - bf16(w) (the low term of a two-term split)
+enum PackMode : int { PACK_BF16 = 0, PACK_F16 = 1, PACK_BF16_LO = 2 };
 hipError_t launch_pack_bf16(const float* w, uint16_t* out, int Ci, int Co, int k, bool transposed,
-                            hipStream_t st, bool f16 = false);
+                            hipStream_t st, int mode = PACK_BF16);
 
 hipError_t launch_snapshot(void* arena, const Item* items, int n, int max_cs, const float* samples,
                            hipStream_t st);

@@ -164,8 +164,10 @@ def test_autograd_function_and_training_steps():
 
 def test_grad_bf16_conv_variant():
     """Training step with the forward (and recomputed) convolutions on BF16
-    matrix cores; activations, statistics and gradients stay FP32.  Gradients
-    within the BF16 tolerance of the oracle; recomputation still bitwise."""
+    matrix cores, each FP32 operand split into two BF16 terms (three MFMAs
+    per product); activations, statistics and gradients stay FP32.  Every
+    output and gradient tensor within the BF16 bound 2e-2 of the oracle;
+    recomputation still bitwise."""
     layers = synth.deepclean_layers()
     params = synth.deepclean_params(0)
     m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
@@ -185,12 +187,53 @@ def test_grad_bf16_conv_variant():
         out.append((noise.cpu().numpy(), dp.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     en = ref.deepclean_forward(params, x, layers, train=True)
-    assert rel(out[0][0], en) <= 2e-2
+    err_noise = rel(out[0][0], en)
     _, dn = ref.bandpass_mse(sb, en, 4096.0, 55.0, 65.0)
     eg = ref.deepclean_grad(params, x, dn, layers)
     errs = grad_errors(out[0][1], eg, layers)
-    # BF16 rounds every conv operand to 2^-8 relative; the forward noise error
-    # is ~7e-3 and a layer-0 gradient passes through all nine layers forward
-    # and back, roughly doubling it, so gradient tensors get 3e-2 (the 2e-2
-    # output bound applies to the forward outputs checked above)
-    assert max(errs.values()) <= 3e-2, errs
+    print("bf16 split training, batch 2: noise", f"{err_noise:.2e}",
+          {k: f"{v:.1e}" for k, v in errs.items()})
+    assert err_noise <= 2e-2
+    assert max(errs.values()) <= 2e-2, errs
+
+
+@pytest.fixture(scope="module")
+def batch32():
+    """The benchmark's training configuration: 32 distinct 8-s windows of 21
+    witness channels and strain, with the oracle's batch-statistics forward
+    and band-passed-loss gradient (FP64)."""
+    B, W = 32, 32768
+    layers = synth.deepclean_layers()
+    params = synth.deepclean_params(0)
+    wit, strain = synth.witness_stream(40, B * W)
+    x = np.ascontiguousarray(wit.reshape(21, B, W).transpose(1, 0, 2))
+    sb = np.ascontiguousarray(strain.reshape(B, W))
+    en = ref.deepclean_forward(params, x, layers, train=True)
+    _, dn = ref.bandpass_mse(sb, en, 4096.0, 55.0, 65.0)
+    eg = ref.deepclean_grad(params, x, dn, layers)
+    return layers, params, x, sb, en, eg
+
+
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_grad_batch32_benchmark_config(batch32, precision, bound):
+    """Batch 32 x 21 x 32768 with recomputation, as the training benchmark
+    runs it: the per-channel statistics chunking and the weight-gradient
+    reduction tree at this size, every gradient tensor against the oracle
+    (FP32 <= 1e-5, BF16-conv variant <= 2e-2)."""
+    layers, params, x, sb, en, eg = batch32
+    m = gs.DeepClean(torch.from_numpy(params).to(DEV), layers)
+    prec = gs.BF16 if precision == "bf16" else gs.FP32
+    flags = gs.TRAIN | gs.RECOMPUTE
+    xt = torch.from_numpy(x).to(DEV)
+    st = torch.from_numpy(sb).to(DEV)
+    noise = torch.empty(sb.shape, device=DEV)
+    ws = m.forward(x=xt, noise=noise, flags=flags, precision=prec)
+    _, dn = gs.bandpass_mse(st, noise)
+    dp = torch.empty_like(m.params)
+    m.backward(xt, dn, ws, dp, flags=flags, precision=prec)
+    torch.cuda.synchronize()
+    err_noise = rel(noise.cpu().numpy(), en)
+    errs = grad_errors(dp.cpu().numpy(), eg, layers)
+    print(f"{precision} training, batch 32: noise {err_noise:.2e}", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert err_noise <= bound
+    assert max(errs.values()) <= bound, errs
