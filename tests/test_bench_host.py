@@ -61,3 +61,13 @@ def test_mix_shape():
     assert len(dc_s) == 179 and len(bb_s) == 77
     assert set(np.unique(dc_s)) <= {256, 512, 1024}
     assert set(np.unique(bb_s)) <= {128, 256, 512}
+
+
+def test_cpu_baseline_uses_one_process_per_core():
+    """The oracle baseline runs in single-threaded worker processes and
+    records how many it used, the host's core count and CPU model."""
+    dc_s, bb_s = bench.make_mix()
+    r = bench.cpu_baseline(dc_s, bb_s, budget_s=0.3, max_procs=2)
+    assert r["kind"] == "oracle" and r["cores"] == min(2, r["host"]["affinity"])
+    assert r["value"] > 0 and r["single_core"]["value"] > 0
+    assert set(r["host"]) == {"nproc", "affinity", "model"}
