@@ -496,6 +496,7 @@ struct LayerD {
   size_t wbf;                 // packed bf16 weights byte offset
   size_t wbf_lo;              // packed low bf16 terms (training variant's split operands)
   size_t wf16;                // packed fp16 weights byte offset (fused-shape networks)
+  size_t wfs, wfs16;          // the fused kernel's own fragment layout (bf16, fp16), where it differs
   bool bf16;                  // BF16 kernel available
 };
 
@@ -606,9 +607,17 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
       m.fused = m.bf16_all && gw::dc_fused_supported(ci.data(), co.data(), ty.data(), k.data(), st.data(),
                                                      pd.data(), op.data(), bn.data(), Ln);
       if (m.fused)
-        for (auto& ly : m.layers) {  // FP16 copies for the fused kernel's FP16 variant
+        for (int l = 0; l < Ln; ++l) {  // FP16 copies for the fused kernel's FP16 variant
+          auto& ly = m.layers[l];
           ly.wf16 = pk;
           pk += r256(2 * gw::conv_bf16_packed_elems(ly.ci, ly.co, ly.k, ly.type == GW_LAYER_CONVT));
+          if (gw::dc_fused_special(l)) {
+            const size_t eb = r256(2 * gw::dc_fused_special_elems(l));
+            ly.wfs = pk;
+            pk += eb;
+            ly.wfs16 = pk;
+            pk += eb;
+          }
         }
     }
   } else if (kind == GW_MODEL_BBHNET) {
@@ -666,7 +675,8 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
 int pack_model(gw_model* m, hipStream_t st) {
   const float* P = m->params;
   if (m->kind == GW_MODEL_DEEPCLEAN) {
-    for (auto& ly : m->layers) {
+    for (int l = 0; l < (int)m->layers.size(); ++l) {
+      auto& ly = m->layers[l];
       float* sc = reinterpret_cast<float*>(m->packed + ly.scale);
       float* sh = reinterpret_cast<float*>(m->packed + ly.shift);
       HIPCHK(gw::launch_fold_bn(P + ly.b, ly.bn ? P + ly.g : nullptr, ly.bn ? P + ly.be : nullptr,
@@ -678,9 +688,14 @@ int pack_model(gw_model* m, hipStream_t st) {
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf_lo), ly.ci,
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, gw::PACK_BF16_LO));
       }
-      if (m->fused)
+      if (m->fused) {
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wf16), ly.ci,
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, gw::PACK_F16));
+        if (gw::dc_fused_special(l)) {
+          HIPCHK(gw::launch_pack_fused(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wfs), l, st, false));
+          HIPCHK(gw::launch_pack_fused(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wfs16), l, st, true));
+        }
+      }
     }
   } else {
     for (auto& sd : m->stages) {
@@ -1066,7 +1081,9 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
     const float* sc[9];
     const float* sh[9];
     for (int l = 0; l < 9; ++l) {
-      wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + (f16 ? m->layers[l].wf16 : m->layers[l].wbf));
+      const LayerD& ly = m->layers[l];
+      const size_t off = gw::dc_fused_special(l) ? (f16 ? ly.wfs16 : ly.wfs) : (f16 ? ly.wf16 : ly.wbf);
+      wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + off);
       sc[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].scale);
       sh[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].shift);
     }

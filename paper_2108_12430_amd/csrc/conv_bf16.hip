@@ -923,7 +923,13 @@ constexpr int cap0(int l) { return (rows_read(l) > NR[l] ? rows_read(l) : NR[l])
 // inputs of the stride-2 layers are stored even rows first, then odd rows
 // (HALF rows each); the other inputs row by row
 constexpr int HALF(int l) { return l < 9 && SC(l) == 2 ? (cap0(l) + 1) / 2 : 0; }
-constexpr int cap(int l) { return HALF(l) ? 2 * HALF(l) : cap0(l); }  // rows of layer l's input buffer
+// the output conv's input rows are stored with one spare row after every 16
+// (row r at r + r / 16): its A-operand reads take rows 16 apart in 16 lanes,
+// which the spare rows spread over distinct bank groups
+constexpr int prow8(int r) { return r + (r >> 4); }
+constexpr int cap(int l) {  // LDS rows of layer l's input buffer
+  return HALF(l) ? 2 * HALF(l) : l == 8 ? prow8(cap0(l) - 1) + 1 : cap0(l);
+}
 constexpr int mx(int a, int b) { return a > b ? a : b; }
 // ping-pong: inputs of layers 0,2,4,6,8 in buffer A, of layers 1,3,5,7 in B
 constexpr int BUFA = mx(mx(mx(cap(0) * rs(C[0]), cap(2) * rs(C[2])), mx(cap(4) * rs(C[4]), cap(6) * rs(C[6]))),
@@ -932,7 +938,18 @@ constexpr int BUFB = mx(mx(cap(1) * rs(C[1]), cap(3) * rs(C[3])), mx(cap(5) * rs
 constexpr int MT(int l) { return (C[l + 1] + 15) / 16; }
 constexpr int NPH(int l) { return l >= 4 && l < 8 ? 2 : 1; }
 constexpr int KS(int l) { return (KT(l) * cip(C[l]) + 31) / 32; }
-constexpr int NFRAG(int l) { return NPH(l) * MT(l) * KS(l); }
+// transposed layers with 8 output channels stack their two phases on the
+// MFMA rows (row = 8 phase + channel), so no accumulator row is padding
+constexpr bool STACK(int l) { return l >= 4 && l < 8 && C[l + 1] == 8; }
+// the output conv (one channel) is a Toeplitz product with output time on
+// both MFMA dimensions: D[m][n] = noise[16 m + n], A[m][(d, i)] = a8[i][16 m +
+// d - 3], B[(d, i)][n] = w[i][d - n] (zero outside the kernel), K = 24
+// offsets x 8 channels; one MFMA tile covers 256 outputs
+constexpr bool TOEP(int l) { return l == 8; }
+constexpr int TB = T / 256;  // 256-output tiles of the output conv
+constexpr int KS8 = 6;       // K steps of the Toeplitz product (offsets 22, 23 carry zero weights)
+// (phase, channel tile) pairs per column tile
+constexpr int QP(int l) { return STACK(l) ? 1 : NPH(l) * MT(l); }
 
 }  // namespace fused
 
@@ -957,7 +974,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 constexpr int mn(int a, int b) { return a < b ? a : b; }
 // 8-channel layers: the valid accumulator rows sit in lanes 0..31, so two
 // column tiles share one epilogue pass (lanes 32..63 take the second tile)
-constexpr bool COMPACT(int l) { return l < 8 && MT(l) == 1 && cip(C[l + 1]) == 8; }
+constexpr bool COMPACT(int l) { return l < 8 && !STACK(l) && MT(l) == 1 && cip(C[l + 1]) == 8; }
 // column tiles per work unit: enough that every layer is one round of units
 // (times GW_FUSED_NTCMUL, at most 4)
 #ifndef GW_FUSED_NTCMUL
@@ -983,10 +1000,10 @@ __host__ __device__ constexpr int koff(int l, int lg, int ks) {
 #define GW_FUSED_MAXSPL 2
 #endif
 constexpr int SPL(int l) {
-  return COMPACT(l) ? 1
-         : GW_FUSED_MAXSPL >= 4 && NPH(l) * MT(l) % 4 == 0 && NG(l) * 4 <= NW
+  return COMPACT(l) || STACK(l) ? 1
+         : GW_FUSED_MAXSPL >= 4 && QP(l) % 4 == 0 && NG(l) * 4 <= NW
              ? 4
-             : (GW_FUSED_MAXSPL >= 2 && NPH(l) * MT(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
+             : (GW_FUSED_MAXSPL >= 2 && QP(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
 }
 }  // namespace fused
 
@@ -1051,7 +1068,7 @@ __device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v,
     t2 = live ? t2 : 0.0f;
     t3 = live ? t3 : 0.0f;
   }
-  const int prow = HO ? (row & 1) * HO + (row >> 1) : row;
+  const int prow = HO ? (row & 1) * HO + (row >> 1) : (l + 1 == 8 ? prow8(row) : row);
   *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(pack2<F16>(t0, t1), pack2<F16>(t2, t3));
 }
 
@@ -1062,25 +1079,22 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
                                           int b, int Wout) {
   using namespace fused;
   constexpr int CIPO = cip(C[l + 1]), M = MT(l), P = NPH(l), NTn = NT(l), SP = SPL(l);
-  if constexpr (l == 8) {
-    // output conv (one channel: accumulator row 0, lanes 0..15): noise and
-    // the fully-online clean output
+  (void)op;
+  (void)b;
+  (void)Wout;
+  static_assert(!TOEP(l), "the output conv has its own layer function");
+  if constexpr (STACK(l)) {
+    // rows 8 ph + o: lanes 0..31 hold phase 0, lanes 32..63 phase 1, each
+    // lane four channels 4 (lg & 1) .. + 3 of column c
+    static_assert(SP == 1 && Q == 1, "stacked layers: one (phases x channels) tile per column");
+    const int o0 = 4 * (lg & 1), ph = lg >> 1;
+    const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
+    const float4 sh4 = *reinterpret_cast<const float4*>(ksh + o0);
 #pragma unroll
     for (int a = 0; a < NTCl; ++a) {
       if (nt0 + a >= NTn) break;
       const int c = (nt0 + a) * 16 + lc;
-      const int u = pos0 + c;
-      if (lg != 0 || c >= NR[9] || u < 0 || u >= Wout) continue;
-      const float v = fmaf(acc[a][0][0], ksc[0], ksh[0]);
-      if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
-      if (op->clean) {
-        const Item& it = op->items[b];
-        const int t0 = Wout - it.s - it.delay;
-        if (u >= t0 && u < t0 + it.s) {
-          const int64_t idx = it.out + (u - t0);
-          op->clean[idx] = op->strain[idx] - v;
-        }
-      }
+      epi_row<l, EDGE, F16>(out, 2 * c + ph - 1, o0, acc[a][0], sc4, sh4, pos0, Lout);
     }
   } else if constexpr (COMPACT(l)) {
     // tiles a, a+1: lanes 0..31 keep tile a's channels 0..7, lanes 32..63
@@ -1136,14 +1150,60 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
 // weight fragments (at most 16, 64 VGPRs) from global memory before its first
 // MFMA; the 92 KB of packed weights stay in L2, shared by every block.  kt
 // holds the layer's row of the B-offset table.
+// The output conv as a Toeplitz product (see TOEP): wave w < TB computes
+// outputs [256 w, 256 w + 256) of the tile with KS8 MFMAs whose A operand
+// (8 channels at one time offset per lane) comes from LDS and whose B
+// operand (the banded weights) from the packed fragments; the epilogue
+// writes the noise and the fully-online clean output.
+template <bool F16>
+__device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, const uint4* wg, const float* ksc,
+                                               const float* ksh, int pos0, const ConvP* op, int b, int Wout) {
+  using namespace fused;
+  constexpr int RSI = rs(C[8]);
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lc = lane & 15, lg = lane >> 4;
+  if (wave >= TB) return;  // wave-uniform
+  const u32x4* wq = reinterpret_cast<const u32x4*>(wg) + lane;
+  u32x4 wf[KS8];
+#pragma unroll
+  for (int ks = 0; ks < KS8; ++ks) wf[ks] = wq[ks * 64];
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS8; ++ks) {
+    // offset d of this lane's eight K entries; offsets past the kernel's
+    // reach (zero weights) read the last real one, a row of finite values
+    const int d = mn(4 * ks + lg, 21);
+    const int r = 256 * wave + 16 * lc + d;
+    const uint4 av = *reinterpret_cast<const uint4*>(in + prow8(r) * RSI);
+    acc = mfma16<F16>(av, __builtin_bit_cast(uint4, wf[ks]), acc);
+  }
+  // D[m = 4 lg + q][n = lc]: output 16 m + n of this wave's 256
+  const float sc = ksc[0], sh = ksh[0];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = pos0 + 256 * wave + 16 * (4 * lg + q) + lc;
+    if (u < 0 || u >= Wout) continue;
+    const float v = fmaf(acc[q], sc, sh);
+    if (op->noise) op->noise[(int64_t)b * Wout + u] = v;
+    if (op->clean) {
+      const Item& it = op->items[b];
+      const int t0 = Wout - it.s - it.delay;
+      if (u >= t0 && u < t0 + it.s) {
+        const int64_t idx = it.out + (u - t0);
+        op->clean[idx] = op->strain[idx] - v;
+      }
+    }
+  }
+}
+
 template <int l, bool F16>
-__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
-                                            const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
-                                            const ConvP* op, int b, int Wout) {
+__device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
+                                               const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
+                                               const ConvP* op, int b, int Wout) {
   using namespace fused;
   constexpr int RSI = rs(C[l]);
   constexpr int KSn = KS(l), NTn = NT(l);
-  constexpr int NTCl = NTC(l), SP = SPL(l), Q = NPH(l) * MT(l) / SP;
+  constexpr int NTCl = NTC(l), SP = SPL(l), Q = QP(l) / SP;
   constexpr int SX = HALF(l) ? 1 : SC(l);  // LDS rows between adjacent columns
   static_assert(KSn <= KSMAX, "offset table width");
   // the wave index is uniform: in an SGPR, unit selection and the weight
@@ -1191,6 +1251,16 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
     else
       fused_epi<l, false, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
   }
+}
+
+template <int l, bool F16>
+__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
+                                            const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
+                                            const ConvP* op, int b, int Wout) {
+  if constexpr (fused::TOEP(l))
+    fused_toeplitz<F16>(tid, in, wg, ksc, ksh, pos0, op, b, Wout);
+  else
+    fused_layer_mm<l, F16>(tid, in, out, wg, kt, ksc, ksh, pos0, Lout, op, b, Wout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1436,6 +1506,47 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
       __syncthreads();
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Weight fragments of the fused kernel's restructured layers: the stacked
+// transposed layers (STACK: [ks][lane][8], row lane % 16 = 8 phase + output
+// channel, K = tap x input channel as for the per-layer kernels) and the
+// Toeplitz output conv (TOEP: [ks][lane][8], the B operand W[(d, i)][n] =
+// w[0][i][d - n] with n = lane % 16, d = 4 ks + lane / 16, i = element).
+// ---------------------------------------------------------------------------
+__global__ void pack_fused_kernel(const float* w, uint16_t* out, int toep, int Ci, int Co, int cipi, int kt,
+                                  int padc, int total, int f16) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, ks = idx >> 9;
+  float v = 0.0f;
+  if (toep) {
+    const int n = lane & 15, d = 4 * ks + (lane >> 4), j = d - n;
+    if (e < Ci && j >= 0 && j < 7) v = w[e * 7 + j];
+  } else {
+    const int row = lane & 15, ph = row >> 3, o = row & 7;
+    const int kappa = 32 * ks + 8 * (lane >> 4) + e, jj = kappa / cipi, i = kappa % cipi;
+    const int d = jj - padc, j = ph + 3 - 2 * d;  // tap of phase ph at input offset d (k7 s2 p3)
+    if (o < Co && i < Ci && jj < kt && j >= 0 && j < 7) v = w[((int64_t)i * Co + o) * 7 + j];
+  }
+  out[idx] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)v) : bf16_rne(v);
+}
+
+bool dc_fused_special(int l) { return l >= 0 && l < 9 && (fused::STACK(l) || fused::TOEP(l)); }
+
+size_t dc_fused_special_elems(int l) {
+  return dc_fused_special(l) ? (size_t)(fused::TOEP(l) ? fused::KS8 : fused::KS(l)) * 512 : 0;
+}
+
+hipError_t launch_pack_fused(const float* w, uint16_t* out, int l, hipStream_t st, bool f16) {
+  using namespace fused;
+  if (!dc_fused_special(l)) return hipErrorInvalidValue;
+  const Geo g = make_geo(true, 7, 2, 3, 1 << 20);
+  const int total = (int)dc_fused_special_elems(l);
+  hipLaunchKernelGGL(pack_fused_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, TOEP(l) ? 1 : 0, C[l],
+                     C[l + 1], cip(C[l]), g.kt, g.padc, total, f16 ? 1 : 0);
+  return hipGetLastError();
 }
 
 bool dc_fused_supported(const int* ci, const int* co, const int* type, const int* k, const int* s,

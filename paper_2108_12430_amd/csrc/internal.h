@@ -87,6 +87,11 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
                                 const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
                                 bool f16 = false);
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
+// layers of the fused network whose weights the fused kernel takes in its own
+// fragment layout (stacked transposed layers, Toeplitz output conv)
+bool dc_fused_special(int l);
+size_t dc_fused_special_elems(int l);
+hipError_t launch_pack_fused(const float* w, uint16_t* out, int l, hipStream_t st, bool f16);
 // mode PACK_BF16: bf16 (RNE); PACK_F16: IEEE half (RNE); PACK_BF16_LO: the
 // bf16 rounding of w - bf16(w) (the low term of a two-term split)
 enum PackMode : int { PACK_BF16 = 0, PACK_F16 = 1, PACK_BF16_LO = 2 };
