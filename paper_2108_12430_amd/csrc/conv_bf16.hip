@@ -911,24 +911,35 @@ constexpr int rs(int c) { return (cip(c) / 8) % 2 ? cip(c) : cip(c) + 8; }
 constexpr int LO[10] = {-93, -45, -21, -9, -3, -3, -3, -3, -3, 0};
 constexpr int NR[10] = {T + 187, T / 2 + 91, T / 4 + 43, T / 8 + 19, T / 16 + 7,
                         T / 8 + 7, T / 4 + 7, T / 2 + 7, T + 6, T};
-// output columns of layer l (convs: one per output row; transposed: one per
-// input-aligned position, producing rows 2c-1 and 2c)
-constexpr int NCOL[9] = {NR[1], NR[2], NR[3], NR[4], T / 16 + 4, T / 8 + 4, T / 4 + 4, T / 2 + 4, T};
+// output columns of layer l: one per output row for the stride-2 convs L1..L3;
+// two output rows (2c, 2c + 1) per column for the first conv, whose MFMA
+// rows stack the two output times; one input-aligned position per column
+// for the transposed layers (rows 2c - 1 and 2c); one per row for the output
+// conv
+constexpr int NCOL[9] = {(NR[1] + 1) / 2, NR[2], NR[3], NR[4], T / 16 + 4, T / 8 + 4, T / 4 + 4, T / 2 + 4, T};
 constexpr int NT(int l) { return (NCOL[l] + 15) / 16; }
 constexpr int SC(int l) { return l < 4 ? 2 : 1; }
-constexpr int KT(int l) { return l < 4 || l == 8 ? 7 : 4; }
+// input rows between adjacent columns, and input rows one column reads
+constexpr int CSTEP(int l) { return l == 0 ? 4 : SC(l); }
+constexpr int KT(int l) { return l == 0 ? 9 : l < 4 || l == 8 ? 7 : 4; }
 // rows of layer l's input buffer that its (padded) columns may read
-constexpr int rows_read(int l) { return SC(l) * (16 * NT(l) - 1) + KT(l); }
+constexpr int rows_read(int l) { return CSTEP(l) * (16 * NT(l) - 1) + KT(l); }
 constexpr int cap0(int l) { return (rows_read(l) > NR[l] ? rows_read(l) : NR[l]); }
-// inputs of the stride-2 layers are stored even rows first, then odd rows
-// (HALF rows each); the other inputs row by row
-constexpr int HALF(int l) { return l < 9 && SC(l) == 2 ? (cap0(l) + 1) / 2 : 0; }
+// inputs read with a column step of 2 or 4 rows are stored split by row
+// residue (row r at (r mod F) PART + r / F), so adjacent columns read
+// adjacent LDS rows; the others row by row
+constexpr int SPLITF(int l) { return l < 9 && CSTEP(l) > 1 ? CSTEP(l) : 1; }
+constexpr int PART(int l) { return (cap0(l) + SPLITF(l) - 1) / SPLITF(l); }
 // the output conv's input rows are stored with one spare row after every 16
 // (row r at r + r / 16): its A-operand reads take rows 16 apart in 16 lanes,
 // which the spare rows spread over distinct bank groups
 constexpr int prow8(int r) { return r + (r >> 4); }
+// LDS row of row r of layer l's input buffer
+__host__ __device__ constexpr int phys(int l, int r) {
+  return SPLITF(l) > 1 ? (r % SPLITF(l)) * PART(l) + r / SPLITF(l) : l == 8 ? prow8(r) : r;
+}
 constexpr int cap(int l) {  // LDS rows of layer l's input buffer
-  return HALF(l) ? 2 * HALF(l) : l == 8 ? prow8(cap0(l) - 1) + 1 : cap0(l);
+  return SPLITF(l) > 1 ? SPLITF(l) * PART(l) : l == 8 ? prow8(cap0(l) - 1) + 1 : cap0(l);
 }
 constexpr int mx(int a, int b) { return a > b ? a : b; }
 // ping-pong: inputs of layers 0,2,4,6,8 in buffer A, of layers 1,3,5,7 in B
@@ -940,7 +951,11 @@ constexpr int NPH(int l) { return l >= 4 && l < 8 ? 2 : 1; }
 constexpr int KS(int l) { return (KT(l) * cip(C[l]) + 31) / 32; }
 // transposed layers with 8 output channels stack their two phases on the
 // MFMA rows (row = 8 phase + channel), so no accumulator row is padding
-constexpr bool STACK(int l) { return l >= 4 && l < 8 && C[l + 1] == 8; }
+// The first conv (8 output channels) stacks two output times the same way
+// (row = 8 n + channel, outputs 2c + n of column c, input offsets d = 2 n + j).
+constexpr bool STACK(int l) { return l == 0 || (l >= 4 && l < 8 && C[l + 1] == 8); }
+// output row of the stacked tile row block q (phase or time offset) of column c
+constexpr int ROFF(int l) { return l == 0 ? 0 : -1; }
 // the output conv (one channel) is a Toeplitz product with output time on
 // both MFMA dimensions: D[m][n] = noise[16 m + n], A[m][(d, i)] = a8[i][16 m +
 // d - 3], B[(d, i)][n] = w[i][d - n] (zero outside the kernel), K = 24
@@ -992,7 +1007,7 @@ constexpr int KSMAX = 8;
 __host__ __device__ constexpr int koff(int l, int lg, int ks) {
   const int kappa = 32 * ks + 8 * lg, jj = kappa / cip(C[l]), i0 = kappa - jj * cip(C[l]);
   const int j = jj < KT(l) ? jj : KT(l) - 1;
-  return (HALF(l) ? (j & 1) * HALF(l) + (j >> 1) : j) * rs(C[l]) + i0;
+  return phys(l, j) * rs(C[l]) + i0;
 }
 // the (phase, channel tile) pairs of a layer with few column groups are
 // split over SPL waves
@@ -1055,7 +1070,7 @@ template <int l, bool EDGE, bool F16>
 __device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v, float4 sc, float4 sh, int pos0,
                                         int Lout) {
   using namespace fused;
-  constexpr int RSO = rs(C[l + 1]), HO = HALF(l + 1);
+  constexpr int RSO = rs(C[l + 1]);
   static_assert(C[l + 1] % 8 == 0, "stored channel groups are never padding");
   if (row < 0 || row >= NR[l + 1]) return;
   float t0 = tanh_scaled(fmaf(v[0], sc.x, sh.x)), t1 = tanh_scaled(fmaf(v[1], sc.y, sh.y));
@@ -1068,7 +1083,7 @@ __device__ __forceinline__ void epi_row(uint16_t* out, int row, int o0, f32x4 v,
     t2 = live ? t2 : 0.0f;
     t3 = live ? t3 : 0.0f;
   }
-  const int prow = HO ? (row & 1) * HO + (row >> 1) : (l + 1 == 8 ? prow8(row) : row);
+  const int prow = phys(l + 1, row);
   *reinterpret_cast<uint2*>(out + prow * RSO + o0) = make_uint2(pack2<F16>(t0, t1), pack2<F16>(t2, t3));
 }
 
@@ -1084,8 +1099,8 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
   (void)Wout;
   static_assert(!TOEP(l), "the output conv has its own layer function");
   if constexpr (STACK(l)) {
-    // rows 8 ph + o: lanes 0..31 hold phase 0, lanes 32..63 phase 1, each
-    // lane four channels 4 (lg & 1) .. + 3 of column c
+    // rows 8 ph + o: lanes 0..31 hold phase (time offset) 0, lanes 32..63
+    // phase 1, each lane four channels 4 (lg & 1) .. + 3 of column c
     static_assert(SP == 1 && Q == 1, "stacked layers: one (phases x channels) tile per column");
     const int o0 = 4 * (lg & 1), ph = lg >> 1;
     const float4 sc4 = *reinterpret_cast<const float4*>(ksc + o0);
@@ -1094,7 +1109,7 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
     for (int a = 0; a < NTCl; ++a) {
       if (nt0 + a >= NTn) break;
       const int c = (nt0 + a) * 16 + lc;
-      epi_row<l, EDGE, F16>(out, 2 * c + ph - 1, o0, acc[a][0], sc4, sh4, pos0, Lout);
+      epi_row<l, EDGE, F16>(out, 2 * c + ph + ROFF(l), o0, acc[a][0], sc4, sh4, pos0, Lout);
     }
   } else if constexpr (COMPACT(l)) {
     // tiles a, a+1: lanes 0..31 keep tile a's channels 0..7, lanes 32..63
@@ -1204,7 +1219,7 @@ __device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint
   constexpr int RSI = rs(C[l]);
   constexpr int KSn = KS(l), NTn = NT(l);
   constexpr int NTCl = NTC(l), SP = SPL(l), Q = QP(l) / SP;
-  constexpr int SX = HALF(l) ? 1 : SC(l);  // LDS rows between adjacent columns
+  constexpr int SX = SPLITF(l) > 1 ? 1 : CSTEP(l);  // LDS rows between adjacent columns
   static_assert(KSn <= KSMAX, "offset table width");
   // the wave index is uniform: in an SGPR, unit selection and the weight
   // addresses are scalar work
@@ -1275,7 +1290,11 @@ __device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 namespace fused {
 constexpr int XG = cip(C[0]) / 4;                  // channel groups of x
-constexpr int XCH = (NR[0] + 7 + 7) / 8;           // chunks covering NR[0] rows at any alignment
+// staged input rows: every row layer 0's columns read (a column's MFMA rows
+// take both output times, so rows past the needed range are read with zero
+// weights and must hold finite values: they get the window's real samples)
+constexpr int XROWS = cap0(0);
+constexpr int XCH = (XROWS + 7 + 7) / 8;           // chunks covering XROWS rows at any alignment
 constexpr int XITEMS = cdiv(XG * XCH, NTHR);       // items per thread
 }  // namespace fused
 
@@ -1344,13 +1363,13 @@ __device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint1
   }
 }
 
-// Issue the loads of a tile's input rows [q0, q0 + NR[0]) of window b.
+// Issue the loads of a tile's input rows [q0, q0 + XROWS) of window b.
 template <int IN>
 __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q0) {
   using namespace fused;
   const int Ci = p.Ci, Lin = p.Lin;
   const int qa = q0 - (((q0 % 8) + 8) % 8);
-  const int nch = (q0 + NR[0] - qa + 7) / 8;
+  const int nch = (q0 + XROWS - qa + 7) / 8;
   int head = 0, ld = p.ldx ? p.ldx : Lin;
   const uint16_t* hbase = nullptr;
   const float* fbase = nullptr;
@@ -1387,13 +1406,13 @@ __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q
   }
 }
 
-// Write the staged rows to LDS (row stride RS, even/odd split at HALF).
+// Write the staged rows to LDS (row stride RS, split by row residue mod 4).
 template <int IN, bool F16>
 __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q0) {
   static_assert(!(F16 && IN == IN_RING), "the ring's 16-bit shadow is BF16");
   using namespace fused;
-  constexpr int RS = rs(C[0]), H = HALF(0), ROWS = NR[0];
-  static_assert(H > 0, "layer 0 reads its input with stride 2");
+  constexpr int RS = rs(C[0]), ROWS = XROWS;
+  static_assert(SPLITF(0) == 4, "layer 0's columns step four input rows");
   const int qa = q0 - (((q0 % 8) + 8) % 8);
   const int nch = (q0 + ROWS - qa + 7) / 8;
 #pragma unroll
@@ -1431,7 +1450,7 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
       }
       const int r = r0 + t;
       if (full || (r >= 0 && r < ROWS))
-        *reinterpret_cast<uint2*>(tile + ((r & 1) * H + (r >> 1)) * RS + 4 * g) = make_uint2(lo, hi);
+        *reinterpret_cast<uint2*>(tile + phys(0, r) * RS + 4 * g) = make_uint2(lo, hi);
     }
   }
 }
@@ -1511,17 +1530,23 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
 // ---------------------------------------------------------------------------
 // Weight fragments of the fused kernel's restructured layers: the stacked
 // transposed layers (STACK: [ks][lane][8], row lane % 16 = 8 phase + output
-// channel, K = tap x input channel as for the per-layer kernels) and the
+// channel, K = tap x input channel as for the per-layer kernels), the stacked
+// first conv (row 8 n + output channel, K = input offset x channel) and the
 // Toeplitz output conv (TOEP: [ks][lane][8], the B operand W[(d, i)][n] =
 // w[0][i][d - n] with n = lane % 16, d = 4 ks + lane / 16, i = element).
 // ---------------------------------------------------------------------------
-__global__ void pack_fused_kernel(const float* w, uint16_t* out, int toep, int Ci, int Co, int cipi, int kt,
+__global__ void pack_fused_kernel(const float* w, uint16_t* out, int kind, int Ci, int Co, int cipi, int kt,
                                   int padc, int total, int f16) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
   const int e = idx & 7, lane = (idx >> 3) & 63, ks = idx >> 9;
   float v = 0.0f;
-  if (toep) {
+  if (kind == 2) {
+    // stacked stride-2 conv: row 8 n + o, K = input offset d (0..kt-1) x channel; tap j = d - 2 n
+    const int row = lane & 15, n = row >> 3, o = row & 7;
+    const int kappa = 32 * ks + 8 * (lane >> 4) + e, d = kappa / cipi, i = kappa % cipi, j = d - 2 * n;
+    if (o < Co && i < Ci && d < kt && j >= 0 && j < 7) v = w[((int64_t)o * Ci + i) * 7 + j];
+  } else if (kind == 1) {
     const int n = lane & 15, d = 4 * ks + (lane >> 4), j = d - n;
     if (e < Ci && j >= 0 && j < 7) v = w[e * 7 + j];
   } else {
@@ -1544,8 +1569,9 @@ hipError_t launch_pack_fused(const float* w, uint16_t* out, int l, hipStream_t s
   if (!dc_fused_special(l)) return hipErrorInvalidValue;
   const Geo g = make_geo(true, 7, 2, 3, 1 << 20);
   const int total = (int)dc_fused_special_elems(l);
-  hipLaunchKernelGGL(pack_fused_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, TOEP(l) ? 1 : 0, C[l],
-                     C[l + 1], cip(C[l]), g.kt, g.padc, total, f16 ? 1 : 0);
+  const int kind = TOEP(l) ? 1 : l == 0 ? 2 : 0;
+  hipLaunchKernelGGL(pack_fused_kernel, dim3((total + 255) / 256), dim3(256), 0, st, w, out, kind, C[l], C[l + 1],
+                     cip(C[l]), l == 0 ? KT(0) : g.kt, g.padc, total, f16 ? 1 : 0);
   return hipGetLastError();
 }
 
