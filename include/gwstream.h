@@ -73,6 +73,8 @@ extern "C" {
                               the rest in deepclean_backward                   */
 #define GW_LAYERWISE 8u    /* deepclean_forward BF16 inference: run one kernel per
                               layer instead of the fused whole-network kernel  */
+#define GW_CACHE_FULL 16u  /* deepclean_forward_cached: recompute every position of
+                              every cache (the from-scratch reference)          */
 #define GW_CAUSAL 4u       /* deepclean_forward inference: compute only what the
                               fully-online output needs (the newest s samples
                               depend on a band of about s + 93 input samples at
@@ -236,6 +238,57 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
                       int32_t n, int32_t W, const int32_t* strides, const int32_t* delays,
                       const float* strain, float* noise, float* clean, int32_t precision, uint32_t flags,
                       void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Incremental DeepClean forward over per-stream activation caches.  The
+ * stateful model hands each request's full window to the static model
+ * (App. B.1), whose update step the paper names as the online bottleneck
+ * (main text, online results).  Between two requests the window only slides:
+ * with a per-stream cache of every layer's activations of the last window,
+ * a request recomputes only the positions whose receptive field reaches the
+ * new samples or the window's left edge, and the full predicted-noise window
+ * comes out as if recomputed.
+ *
+ * deepclean_cache_bytes: device bytes of one stream's cache for windows of W
+ * samples: every layer's activations as a ring, C_out x L_out BF16 (FP32 for
+ * the output conv).  W must be a multiple of 16; at most 16 layers.
+ *
+ * gw_stream_attach_cache: attach a caller-owned cache (device, 256-byte
+ * aligned, at least deepclean_cache_bytes for the slot's W) to an open slot,
+ * or detach it (cache NULL).  The memory must stay valid until it is
+ * detached, replaced or the slot is closed and the work that uses it has
+ * completed.  Attaching invalidates the cache (the next call recomputes it).
+ *
+ * deepclean_cache_bands: for the DeepClean network `desc` (as for
+ * gw_model_create), the dirty positions [0, zl[l]) and [zr[l], L_l) of every
+ * layer l (host [layers] each) after the window advanced by `shift` samples
+ * (a multiple of 16 below W; -1: everything).  Host only (no device work).
+ *
+ * deepclean_forward_cached: for n slots (host [n], distinct, C == model C_in,
+ * window W, each with a cache attached) whose snapshots are current on
+ * hip_stream, bring every cache to the current window and write the outputs.
+ * A cache that holds the window from `a` samples ago, a a multiple of 16
+ * below W, is updated incrementally (its dirty bands only); any other cache
+ * (never computed, attached anew, a not a multiple of 16 or a >= W), and
+ * every cache under GW_CACHE_FULL, is recomputed at every position.  Each
+ * value is the same function of its inputs either way, so the two are
+ * bitwise equal.  Arithmetic: BF16 activations (the snapshot's BF16 shadow
+ * for the first layer) and BF16-rounded weights, FP32 accumulation in a
+ * fixed order, FP32 folded normalisation and tanh (running statistics).
+ * Outputs, as deepclean_forward's (either may be NULL): noise device [n][W]
+ * float32; clean packed by strides (host [n]) with strain, and delays (host
+ * [n] or NULL).  flags: 0 or GW_CACHE_FULL.  Errors: GW_EINVAL (shapes,
+ * strides, delays, missing or small cache, duplicate slot), GW_ESTATE (closed
+ * slot, wrong model kind), GW_EUNSUPPORTED (more than 16 layers).  Calls on
+ * one pool are serialised by the caller; the caches' contents are undefined
+ * if a call fails.
+ */
+int deepclean_cache_bytes(const gw_model* model, int32_t W, size_t* bytes);
+int gw_stream_attach_cache(gw_pool* pool, int32_t slot, void* cache, size_t bytes);
+int deepclean_cache_bands(const int32_t* desc, int32_t desc_len, int32_t W, int32_t shift, int32_t* zl, int32_t* zr);
+int deepclean_forward_cached(const gw_model* model, gw_pool* pool, const int32_t* slots, int32_t n, int32_t W,
+                             const int32_t* strides, const int32_t* delays, const float* strain, float* noise,
+                             float* clean, uint32_t flags, void* hip_stream);
 
 /*
  * gw_decimate2: streaming decimation by 2 with a causal FIR, the step of the

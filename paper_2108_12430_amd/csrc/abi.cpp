@@ -92,13 +92,20 @@ struct Stager {
   }
   int stage(const std::vector<Item>& items, hipStream_t st, const Item** out, StageGuard* guard) {
     if ((int)items.size() > cap) return fail(GW_EINVAL, "too many items in one call");
+    const void* d = nullptr;
+    CHK(stage_raw(items.data(), items.size() * sizeof(Item), st, &d, guard));
+    *out = reinterpret_cast<const Item*>(d);
+    return GW_OK;
+  }
+  // Any table of at most cap * sizeof(Item) bytes (same slots and reuse rule).
+  int stage_raw(const void* data, size_t bytes, hipStream_t st, const void** out, StageGuard* guard) {
+    if (bytes > (size_t)cap * sizeof(Item)) return fail(GW_EINVAL, "too many items in one call");
     const int k = next;
     next = (next + 1) % K;
     if (used[k]) HIPCHK(hipEventSynchronize(ev[k]));
     ++gen[k];
-    std::memcpy(host + (size_t)k * cap, items.data(), items.size() * sizeof(Item));
-    HIPCHK(hipMemcpyAsync(dev + (size_t)k * cap, host + (size_t)k * cap, items.size() * sizeof(Item),
-                          hipMemcpyHostToDevice, st));
+    std::memcpy(host + (size_t)k * cap, data, bytes);
+    HIPCHK(hipMemcpyAsync(dev + (size_t)k * cap, host + (size_t)k * cap, bytes, hipMemcpyHostToDevice, st));
     // provisional record (covers the copy if the call ends before its launches);
     // the guard records again after the launches
     HIPCHK(hipEventRecord(ev[k], st));
@@ -210,6 +217,12 @@ struct gw_pool {
     hipEvent_t fill = nullptr;  // recorded after the zero-fill of gw_stream_open
     int last_k = -1;            // the last call that read or wrote the ring: stager
     uint64_t last_gen = 0;      // slot and generation (see Stager)
+    // activation cache of the incremental DeepClean forward (caller-owned)
+    void* cache = nullptr;
+    size_t cache_bytes = 0;
+    bool cache_valid = false;  // holds the window that ended cache_seen samples into the stream
+    int cache_T = 0;           // its window start modulo W (ring heads)
+    int64_t cache_seen = 0;
   };
   // A closed slot's region whose last users may still be running: a later
   // open that reuses any of its bytes orders its zero-fill after them.
@@ -388,6 +401,9 @@ extern "C" int gw_stream_open(gw_pool* pool, int32_t C, int32_t W, void* hip_str
   s.fill = fill;
   s.last_k = -1;
   s.last_gen = 0;
+  s.cache = nullptr;
+  s.cache_bytes = 0;
+  s.cache_valid = false;
   *slot = id;
   return GW_OK;
 }
@@ -1156,6 +1172,161 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
                                       lout[l], st));
     }
     in = a;
+  }
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Incremental forward over per-stream activation caches
+// ---------------------------------------------------------------------------
+namespace {
+
+// Cache geometry of a DeepClean model for windows of W samples, and the
+// byte offset of every layer's ring in a stream's cache.
+int cache_layout(const gw_model* m, int W, gw::CacheLayerP& P, size_t* total) {
+  if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
+  const int L = (int)m->layers.size();
+  if (L > gw::kCacheMaxLayers) return fail(GW_EUNSUPPORTED, "activation caches support at most 16 layers");
+  std::vector<int> lin, lout;
+  CHK(dc_lengths(m, W, lin, lout));
+  size_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    const LayerD& ly = m->layers[l];
+    if (W % lout[l]) return fail(GW_EUNSUPPORTED, "layer length must divide the window");
+    gw::CacheGeo& g = P.geo[l];
+    g.type = ly.type == GW_LAYER_CONVT ? 1 : 0;
+    g.ci = ly.ci;
+    g.co = ly.co;
+    g.k = ly.k;
+    g.s = ly.s;
+    g.p = ly.p;
+    g.op = ly.op;
+    g.Lin = lin[l];
+    g.Lout = lout[l];
+    g.f = W / lout[l];
+    g.bn = ly.bn ? 1 : 0;
+    g.f32 = l == L - 1 ? 1 : 0;
+    if (16 % g.f) return fail(GW_EUNSUPPORTED, "layer grids must divide the 16-sample shift unit");
+    P.off[l] = off;
+    off += r256((size_t)g.co * g.Lout * (g.f32 ? 4 : 2));
+  }
+  P.W = W;
+  *total = off;
+  return GW_OK;
+}
+
+}  // namespace
+
+extern "C" int deepclean_cache_bytes(const gw_model* m, int32_t W, size_t* bytes) {
+  if (!m || !bytes) return fail(GW_EINVAL, "null argument");
+  gw::CacheLayerP P{};
+  return cache_layout(m, W, P, bytes);
+}
+
+extern "C" int deepclean_cache_bands(const int32_t* desc, int32_t desc_len, int32_t W, int32_t shift, int32_t* zl,
+                                     int32_t* zr) {
+  if (!desc || !zl || !zr) return fail(GW_EINVAL, "null argument");
+  gw_model m;  // host-side layout only
+  CHK(build_layout(GW_MODEL_DEEPCLEAN, desc, desc_len, m));
+  gw::CacheLayerP P{};
+  size_t total = 0;
+  CHK(cache_layout(&m, W, P, &total));
+  if (shift >= 0 && (shift % 16 || shift >= W)) return fail(GW_EINVAL, "shift must be a multiple of 16 below W, or -1");
+  for (int l = 0; l < (int)m.layers.size(); ++l) gw::cache_band(P.geo, l, shift, W, &zl[l], &zr[l]);
+  return GW_OK;
+}
+
+extern "C" int gw_stream_attach_cache(gw_pool* pool, int32_t slot, void* cache, size_t bytes) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  CHK(pool->check_slot(slot));
+  if (cache && reinterpret_cast<uintptr_t>(cache) % 256) return fail(GW_EINVAL, "cache not 256-byte aligned");
+  auto& s = pool->slots[slot];
+  s.cache = cache;
+  s.cache_bytes = cache ? bytes : 0;
+  s.cache_valid = false;
+  return GW_OK;
+}
+
+extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const int32_t* slots, int32_t n,
+                                        int32_t W, const int32_t* strides, const int32_t* delays,
+                                        const float* strain, float* noise, float* clean, uint32_t flags,
+                                        void* hip_stream) {
+  const hipStream_t st = S(hip_stream);
+  if (!m || !pool || !slots) return fail(GW_EINVAL, "null model, pool or slots");
+  if (n == 0) return GW_OK;
+  if (n < 0) return fail(GW_EINVAL, "negative n");
+  if (flags & ~GW_CACHE_FULL) return fail(GW_EINVAL, "bad flags");
+  if (clean && (!strides || !strain)) return fail(GW_EINVAL, "clean output needs strides and strain");
+  if (delays && !clean) return fail(GW_EINVAL, "delays apply to the clean output");
+  gw::CacheLayerP P{};
+  size_t need = 0;
+  CHK(cache_layout(m, W, P, &need));
+  std::vector<gw::CacheItem> items(n);
+  std::vector<char> seen(pool->max_slots, 0);
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    CHK(pool->check_slot(slots[i]));
+    if (seen[slots[i]]) return fail(GW_EINVAL, "slot appears twice in one call");
+    seen[slots[i]] = 1;
+    const auto& sl = pool->slots[slots[i]];
+    if (sl.C != m->c_in || sl.W != W) return fail(GW_EINVAL, "slot C/W does not match the model and W");
+    if (!sl.cache || sl.cache_bytes < need)
+      return fail(GW_EINVAL, "slot has no activation cache of deepclean_cache_bytes bytes attached");
+    gw::CacheItem& it = items[i];
+    std::memset(&it, 0, sizeof(it));
+    it.cache = sl.cache;
+    it.shadow = pool->shadow_elem(sl);
+    it.in_head = sl.head;  // oldest sample of the current window
+    const int64_t adv = sl.n_seen - sl.cache_seen;
+    if (!sl.cache_valid || (flags & GW_CACHE_FULL) || adv < 0 || adv >= W || adv % 16) {
+      it.shift = -1;
+      it.T = 0;
+    } else {
+      it.shift = (int32_t)adv;
+      it.T = (int32_t)((sl.cache_T + adv) % W);
+    }
+    if (clean) {
+      if (strides[i] < 1 || strides[i] > W) return fail(GW_EINVAL, "stride must be in [1, W]");
+      it.s = strides[i];
+      it.delay = delays ? delays[i] : 0;
+      if (it.delay < 0 || it.delay > W - it.s) return fail(GW_EINVAL, "delay must be in [0, W - stride]");
+      it.out = off;
+      off += strides[i];
+    }
+  }
+  const int L = (int)m->layers.size();
+  // widest dirty set of each layer over the items (the launch grid)
+  std::vector<int> maxd(L, 0);
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < L; ++l) {
+      int zl, zr;
+      gw::cache_band(P.geo, l, items[i].shift, W, &zl, &zr);
+      maxd[l] = std::max(maxd[l], zl + P.geo[l].Lout - zr);
+    }
+  const void* dev = nullptr;
+  StageGuard guard;
+  CHK(pool->stager.stage_raw(items.data(), items.size() * sizeof(gw::CacheItem), st, &dev, &guard));
+  // until every launch is enqueued the caches hold no known window (an error
+  // below leaves them to be recomputed in full by the next call)
+  for (int i = 0; i < n; ++i) pool->slots[slots[i]].cache_valid = false;
+  pool->mark_used(slots, n, guard);
+  const auto* dit = reinterpret_cast<const gw::CacheItem*>(dev);
+  for (int l = 0; l < L; ++l) {
+    const LayerD& ly = m->layers[l];
+    P.layer = l;
+    P.w = m->params + ly.w;
+    P.scale = reinterpret_cast<const float*>(m->packed + ly.scale);
+    P.shift = reinterpret_cast<const float*>(m->packed + ly.shift);
+    LAUNCH(nm("cache_layer", "L", l), st, gw::launch_cache_layer(dit, n, pool->arena, P, maxd[l], st));
+  }
+  if (noise || clean)
+    LAUNCH("cache_emit", st, gw::launch_cache_emit(dit, n, W, P.off[L - 1], strain, noise, clean, st));
+  // every cache now holds the current window
+  for (int i = 0; i < n; ++i) {
+    auto& sl = pool->slots[slots[i]];
+    sl.cache_valid = true;
+    sl.cache_T = items[i].T;
+    sl.cache_seen = sl.n_seen;
   }
   return GW_OK;
 }

@@ -74,6 +74,85 @@ struct ConvP {
   int ldx;
 };
 
+// ---- incremental DeepClean over per-stream activation caches ----
+// Geometry of one layer of the cached network: type 0 conv (output k reads
+// inputs s k - p + j), 1 transposed conv (output u = s t - p + j); f is the
+// window length over the layer's output length (the grid's step in samples);
+// bn: normalisation + tanh, stored BF16; f32: stored FP32 (the output conv).
+struct CacheGeo {
+  int type, ci, co, k, s, p, op, Lin, Lout, f, bn, f32;
+};
+constexpr int kCacheMaxLayers = 16;
+struct CacheLayerP {
+  CacheGeo geo[kCacheMaxLayers];
+  size_t off[kCacheMaxLayers];  // byte offset of layer l's ring in a stream's cache
+  int layer, W;
+  const float* w;               // the layer's FP32 weights (PyTorch layout)
+  const float* scale;           // folded normalisation: y = acc * scale + shift
+  const float* shift;
+};
+// Per-item descriptor of a cached call (staged with the pool's item tables).
+struct CacheItem {
+  void* cache;        // the stream's cache (device)
+  int64_t shadow;     // BF16 shadow of the stream's snapshot ring (arena elements)
+  int64_t out;        // offset of the item's [s] block in strain/clean
+  int32_t in_head;    // ring index of the snapshot's oldest sample
+  int32_t T;          // the cache's window start modulo W (a multiple of 16): layer l's ring head is T / f_l
+  int32_t shift;      // samples the window advanced since the cache was last made current; -1: recompute all
+  int32_t s, delay;   // clean output span [W - s - delay, W - delay)
+  int32_t pad_;
+};
+static_assert(sizeof(CacheItem) == 48, "CacheItem layout");
+
+__host__ __device__ inline int cache_cdiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+// Dirty output positions of layer `layer` after the window advanced by
+// `shift` samples (a multiple of the total stride): [0, *zl) and [*zr, Lout).
+// An output keeps its cached value when every input it reads kept its value:
+// inputs in the dirty bands of the previous layer change, the first layer's
+// newest `shift` samples are new, and inputs before the window's start are
+// zero padding now but were real samples before (so the left zone grows
+// from the padding inward); inputs past the window's end are padding in both.
+// Past the end, the last shift / f positions of a layer did not exist.  The
+// bands are a superset of the positions that change (never a subset).
+__host__ __device__ inline void cache_band(const CacheGeo* g, int layer, int shift, int W, int* zl, int* zr) {
+  const int L = g[layer].Lout;
+  if (shift < 0) {  // recompute everything
+    *zl = L;
+    *zr = L;
+    return;
+  }
+  int lo_in = 0, hi_in = W - shift, Lin = W;
+  for (int l = 0; l <= layer; ++l) {
+    const CacheGeo& G = g[l];
+    const int Lo = G.Lout;
+    int lo, hi;
+    if (G.type == 0) {
+      lo = cache_cdiv(lo_in + G.p, G.s);                                 // s k - p >= lo_in
+      hi = hi_in < Lin ? cache_cdiv(hi_in - (G.k - 1 - G.p), G.s) : Lo;  // s k - p + k - 1 >= hi_in
+    } else {
+      lo = G.s * (lo_in - 1) + G.k - G.p;                                // min input >= lo_in
+      hi = hi_in < Lin ? G.s * hi_in - G.p : Lo;                         // max input >= hi_in
+    }
+    const int fresh = Lo - shift / G.f;
+    hi = hi < fresh ? hi : fresh;
+    lo = lo < 0 ? 0 : (lo > Lo ? Lo : lo);
+    hi = hi < 0 ? 0 : (hi > Lo ? Lo : hi);
+    if (hi <= lo) {  // the bands meet: every position is dirty
+      lo = Lo;
+      hi = Lo;
+    }
+    lo_in = lo;
+    hi_in = hi;
+    Lin = Lo;
+  }
+  *zl = lo_in;
+  *zr = hi_in;
+}
+hipError_t launch_cache_layer(const CacheItem* items, int n, const void* arena, const CacheLayerP& P, int max_dirty,
+                              hipStream_t st);
+hipError_t launch_cache_emit(const CacheItem* items, int n, int W, size_t off_noise, const float* strain,
+                             float* noise, float* clean, hipStream_t st);
+
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);

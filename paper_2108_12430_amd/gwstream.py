@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgwstream.so")
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_ESTATE, GW_EHIP, GW_EUNSUPPORTED = range(6)
 FP32, BF16, FP16 = 0, 1, 2
 MODEL_DEEPCLEAN, MODEL_BBHNET = 1, 2
-TRAIN, RECOMPUTE, CAUSAL, LAYERWISE = 1, 2, 4, 8
+TRAIN, RECOMPUTE, CAUSAL, LAYERWISE, CACHE_FULL = 1, 2, 4, 8, 16
 _CODES = {1: "GW_EINVAL", 2: "GW_ENOMEM", 3: "GW_ESTATE", 4: "GW_EHIP", 5: "GW_EUNSUPPORTED"}
 
 EXPORTS = [
@@ -28,6 +28,7 @@ EXPORTS = [
     "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
     "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
+    "deepclean_cache_bytes", "gw_stream_attach_cache", "deepclean_cache_bands", "deepclean_forward_cached",
     "deepclean_backward_scratch",
     "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "gw_bandpass_mse_noalloc", "bbhnet_workspace", "bbhnet_forward",
@@ -74,6 +75,10 @@ def lib():
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
             "deepclean_overlap_average": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "gw_decimate2": ([i32, i32, i32, i32, vp, vp, vp, vp, vp], C.c_int),
+            "deepclean_cache_bytes": ([vp, i32, P(sz)], C.c_int),
+            "gw_stream_attach_cache": ([vp, i32, vp, sz], C.c_int),
+            "deepclean_cache_bands": ([vp, i32, i32, i32, vp, vp], C.c_int),
+            "deepclean_forward_cached": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, u32, vp], C.c_int),
             "deepclean_backward_scratch": ([vp, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_backward": ([vp, i32, i32, vp, vp, vp, vp, u32, i32, vp, sz, vp], C.c_int),
             "gw_bandpass_workspace": ([i32, i32, f32, f32, f32, P(sz)], C.c_int),
@@ -191,6 +196,16 @@ class Pool:
             check(lib().gw_stream_window(self.h, slot, _ptr(out), None, _stream(stream)))
         return out
 
+    def attach_cache(self, slot, cache):
+        """gw_stream_attach_cache: a uint8 device tensor (or None to detach)
+        holding the slot's activation cache; it must outlive its use."""
+        if cache is None:
+            check(lib().gw_stream_attach_cache(self.h, slot, None, 0))
+        else:
+            if cache.dtype != torch.uint8 or not cache.is_cuda or not cache.is_contiguous():
+                raise ValueError("cache must be a contiguous uint8 device tensor")
+            check(lib().gw_stream_attach_cache(self.h, slot, _ptr(cache), cache.numel()))
+
     def usage(self):
         u, f = C.c_size_t(), C.c_size_t()
         check(lib().gw_pool_usage(self.h, C.byref(u), C.byref(f)))
@@ -257,6 +272,18 @@ class _Model:
             pass
 
 
+def cache_bands(layers, W, shift):
+    """deepclean_cache_bands for a layer list: [(zl, zr)] per layer, the dirty
+    positions [0, zl) and [zr, L) after the window advanced by shift samples
+    (-1: everything).  Needs no GPU."""
+    d = deepclean_desc(layers)
+    zl = np.zeros(len(layers), np.int32)
+    zr = np.zeros(len(layers), np.int32)
+    check(lib().deepclean_cache_bands(d.ctypes.data_as(C.c_void_p), len(d), W, shift, zl.ctypes.data_as(C.c_void_p),
+                                      zr.ctypes.data_as(C.c_void_p)))
+    return list(zip(zl.tolist(), zr.tolist()))
+
+
 def model_n_params(kind, desc):
     d = np.ascontiguousarray(desc, dtype=np.int32)
     n = C.c_int64()
@@ -276,6 +303,36 @@ class DeepClean(_Model):
         b = C.c_size_t()
         check(lib().deepclean_workspace(self.h, n, W, precision, flags, C.byref(b)))
         return b.value
+
+    def cache_bytes(self, W):
+        """deepclean_cache_bytes: one stream's activation cache."""
+        b = C.c_size_t()
+        check(lib().deepclean_cache_bytes(self.h, W, C.byref(b)))
+        return b.value
+
+    def new_cache(self, W):
+        """A device buffer of cache_bytes(W) bytes (256-byte aligned)."""
+        return _buffer(self.cache_bytes(W), self.device)
+
+    def cache_bands(self, W, shift):
+        """deepclean_cache_bands: [(zl, zr)] per layer (host query)."""
+        return cache_bands(self.layers, W, shift)
+
+    def forward_cached(self, *, pool, slots, W, strides=None, strain=None, noise=None, clean=None, delays=None,
+                       full=False, stream=None):
+        """Enqueue deepclean_forward_cached (every slot needs an attached
+        cache); outputs are caller-provided tensors or None."""
+        sl, psl = _host_i32(slots)
+        st = pst = dl = pdl = None
+        if strides is not None:
+            st, pst = _host_i32(strides)
+        if delays is not None:
+            dl, pdl = _host_i32(delays)
+        for t, nm in ((strain, "strain"), (noise, "noise"), (clean, "clean")):
+            if t is not None:
+                _f32(t, nm)
+        check(lib().deepclean_forward_cached(self.h, pool.h, psl, len(sl), W, pst, pdl, _ptr(strain), _ptr(noise),
+                                             _ptr(clean), CACHE_FULL if full else 0, _stream(stream)))
 
     def forward(self, *, x=None, pool=None, slots=None, n=None, W=None, strides=None, strain=None,
                 noise=None, clean=None, precision=FP32, flags=0, ws=None, stream=None, delays=None):
