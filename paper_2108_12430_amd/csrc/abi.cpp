@@ -1207,6 +1207,8 @@ int cache_layout(const gw_model* m, int W, gw::CacheLayerP& P, size_t* total) {
     g.bn = ly.bn ? 1 : 0;
     g.f32 = l == L - 1 ? 1 : 0;
     if (16 % g.f) return fail(GW_EUNSUPPORTED, "layer grids must divide the 16-sample shift unit");
+    if (!gw::cache_layer_fits(g) || !ly.bf16)
+      return fail(GW_EUNSUPPORTED, "no cached kernel for this layer shape (k7 p3 layers with compiled channel tiles)");
     P.off[l] = off;
     off += r256((size_t)g.co * g.Lout * (g.f32 ? 4 : 2));
   }
@@ -1295,13 +1297,14 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     }
   }
   const int L = (int)m->layers.size();
-  // widest dirty set of each layer over the items (the launch grid)
+  // most chunks of dirty positions of each layer over the items (the launch grid)
   std::vector<int> maxd(L, 0);
+  constexpr int CK = gw::kCacheChunk;
   for (int i = 0; i < n; ++i)
     for (int l = 0; l < L; ++l) {
       int zl, zr;
       gw::cache_band(P.geo, l, items[i].shift, W, &zl, &zr);
-      maxd[l] = std::max(maxd[l], zl + P.geo[l].Lout - zr);
+      maxd[l] = std::max(maxd[l], (zl + CK - 1) / CK + (P.geo[l].Lout - zr + CK - 1) / CK);
     }
   const void* dev = nullptr;
   StageGuard guard;
@@ -1314,13 +1317,16 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
   for (int l = 0; l < L; ++l) {
     const LayerD& ly = m->layers[l];
     P.layer = l;
-    P.w = m->params + ly.w;
+    P.wpk = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf);
     P.scale = reinterpret_cast<const float*>(m->packed + ly.scale);
     P.shift = reinterpret_cast<const float*>(m->packed + ly.shift);
     LAUNCH(nm("cache_layer", "L", l), st, gw::launch_cache_layer(dit, n, pool->arena, P, maxd[l], st));
   }
-  if (noise || clean)
-    LAUNCH("cache_emit", st, gw::launch_cache_emit(dit, n, W, P.off[L - 1], strain, noise, clean, st));
+  if (noise || clean) {
+    int max_s = 0;
+    for (int i = 0; i < n; ++i) max_s = std::max(max_s, (int)items[i].s);
+    LAUNCH("cache_emit", st, gw::launch_cache_emit(dit, n, W, max_s, P.off[L - 1], strain, noise, clean, st));
+  }
   // every cache now holds the current window
   for (int i = 0; i < n; ++i) {
     auto& sl = pool->slots[slots[i]];
