@@ -286,8 +286,10 @@ def bbhnet_flops(L=BB_W):
     return 2.0 * (macs + 128)
 
 
-def bbhnet_batch_bench(dev, batches=(64, 256, 1024), iters=20):
-    """BBHnet BF16 forward on dense batches of 2 x 2048 windows."""
+def bbhnet_batch_bench(dev, batches=(64, 256, 1024), iters=100, warm_s=0.2):
+    """BBHnet BF16 forward on dense batches of 2 x 2048 windows: at least
+    warm_s seconds of the same launches first (steady clocks), then iters
+    launches timed with HIP events on the launch stream."""
     import torch
 
     from paper_2108_12430_amd import gwstream as gs
@@ -298,14 +300,18 @@ def bbhnet_batch_bench(dev, batches=(64, 256, 1024), iters=20):
         x = torch.from_numpy(synth.bbh_windows(3 + B, B)[0]).to(dev)
         logits = torch.empty(B, device=dev)
         ws = torch.empty(bb.workspace_bytes(B, BB_W, gs.BF16), dtype=torch.uint8, device=dev)
-        for _ in range(3):
-            bb.forward(x=x, logits=logits, precision=gs.BF16, ws=ws)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
+        while time.perf_counter() - t0 < warm_s:
+            for _ in range(10):
+                bb.forward(x=x, logits=logits, precision=gs.BF16, ws=ws)
+            torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(iters):
             bb.forward(x=x, logits=logits, precision=gs.BF16, ws=ws)
+        e1.record()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / iters
+        dt = e0.elapsed_time(e1) * 1e-3 / iters
         tf = B * bbhnet_flops() / dt / 1e12
         out.append({"batch": B, "ms": 1e3 * dt, "windows_per_s": B / dt, "samples_per_s": B * BB_W / dt,
                     "tflops": tf, "frac_of_bf16_peak": tf / BF16_PEAK_TFLOPS})

@@ -189,6 +189,13 @@ int gw_model_free(gw_model* model);
  * on another host thread races.  Errors: GW_EINVAL for a null model or
  * ncu < 0. */
 int gw_model_set_cu_budget(gw_model* model, int32_t ncu);
+/* gw_model_set_layerwise: for a BBHnet model of the reference shape (2 input
+ * channels, stages of 32, 64 and 128 channels), BF16 forwards run by default
+ * as one fused kernel that keeps every intermediate activation on chip and
+ * reads ring windows in place; on != 0 selects the per-layer kernels instead
+ * (the same results within the BF16 tolerance).  DeepClean takes GW_LAYERWISE
+ * per call instead (GW_EINVAL here).  Same threading rule as the CU budget. */
+int gw_model_set_layerwise(gw_model* model, int32_t on);
 /* Number of float32 parameters a description implies. */
 int gw_model_n_params(int32_t kind, const int32_t* desc, int32_t desc_len, int64_t* n_params);
 

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgwstream.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["abi.cpp", "conv_fp32.hip", "conv_bf16.hip", "misc.hip", "train.hip", "cache.hip"]
+SOURCES = ["abi.cpp", "conv_fp32.hip", "conv_bf16.hip", "misc.hip", "train.hip", "cache.hip", "bbh_fused.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -539,7 +539,8 @@ struct gw_model {
   char* packed = nullptr;
   Stager stager;
   bool bf16_all = false;
-  bool fused = false;  // reference DeepClean shape: whole-network BF16 kernel available
+  bool fused = false;  // reference DeepClean / BBHnet shape: whole-network BF16 kernel available
+  bool layerwise = false;  // BBHnet BF16: run the per-layer kernels instead of the fused one
   int cu_budget = 0;   // CUs the persistent kernels size their grid for (0: all)
 };
 
@@ -675,6 +676,11 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
       ci = sd.co;
     }
     m.c_last = ci;
+    {
+      std::vector<int> co;
+      for (auto& sd : m.stages) co.push_back(sd.co);
+      m.fused = m.bf16_all && gw::bbh_fused_supported(m.c_in, co.data(), Sn);
+    }
     m.head_w = off;
     off += ci;
     m.head_b = off;
@@ -842,6 +848,13 @@ extern "C" int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_l
 extern "C" int gw_model_refresh(gw_model* m, void* hip_stream) {
   if (!m) return fail(GW_EINVAL, "null model");
   return pack_model(m, S(hip_stream));
+}
+
+extern "C" int gw_model_set_layerwise(gw_model* m, int32_t on) {
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (m->kind != GW_MODEL_BBHNET) return fail(GW_EINVAL, "DeepClean takes GW_LAYERWISE per call");
+  m->layerwise = on != 0;
+  return GW_OK;
 }
 
 extern "C" int gw_model_set_cu_budget(gw_model* m, int32_t ncu) {
@@ -1721,6 +1734,36 @@ int bb_layout(const gw_model* m, int n, int W, bool pool, int precision, BbWs& b
 }
 }  // namespace
 
+namespace {
+// The whole BBHnet in one kernel (blocks of 64 last-stage positions), then
+// the fixed-order sum of each window's pooled-head shares into its logit.
+int bbh_fused_forward(const gw_model* m, const void* arena, const Item* items, const float* x, int n, int W,
+                      char* gap, float* logits, hipStream_t st) {
+  gw::BbFusedP fp{};
+  fp.arena = arena;
+  fp.items = items;
+  fp.x = x;
+  const float* P = m->params;
+  for (int s = 0; s < 3; ++s) {
+    const StageD& sd = m->stages[s];
+    fp.wa[s] = reinterpret_cast<const uint16_t*>(m->packed + sd.wa_bf);
+    fp.wb[s] = reinterpret_cast<const uint16_t*>(m->packed + sd.wb_bf);
+    fp.ws[s] = reinterpret_cast<const uint16_t*>(m->packed + sd.ws_bf);
+    fp.ba[s] = P + sd.ba;
+    fp.bb[s] = P + sd.bb;
+    fp.bs[s] = P + sd.bs;
+  }
+  fp.hw = P + m->head_w;
+  fp.part = reinterpret_cast<float*>(gap);
+  fp.n = n;
+  fp.W = W;
+  fp.tiles = gw::bbh_fused_tiles(W);
+  LAUNCH("bbh_fused", st, gw::launch_bbh_fused(fp, st));
+  LAUNCH("gap_finalize", st, gw::launch_gap_finalize(fp.part, fp.tiles, P + m->head_b, logits, n, W / 8, st));
+  return GW_OK;
+}
+}  // namespace
+
 extern "C" int bbhnet_workspace(const gw_model* m, int32_t n, int32_t W, int32_t precision,
                                 size_t* bytes) {
   if (!m || !bytes) return fail(GW_EINVAL, "null argument");
@@ -1754,6 +1797,7 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
   const float* in = x;
   StageGuard guard;  // the gathered window is read by the first stage only, but
                      // the table stays reserved until the call's last launch
+  const bool fused = precision == GW_BF16 && m->fused && !m->layerwise && gw::bbh_fused_tiles(W) <= kGapParts;
   if (pool) {
     std::vector<Item> items(n);
     std::vector<char> seen(pool->max_slots, 0);
@@ -1773,9 +1817,17 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
     const Item* dev = nullptr;
     CHK(pool->stager.stage(items, st, &dev, &guard));
     pool->mark_used(slots, n, guard);
+    if (fused) {
+      // the fused kernel reads every window straight from its ring
+      CHK(bbh_fused_forward(m, pool->arena, dev, nullptr, n, W, wsb + b.gap, logits, st));
+      return GW_OK;
+    }
     float* g = reinterpret_cast<float*>(wsb + b.gath);
     LAUNCH("gather", st, gw::launch_gather(pool->arena, dev, n, m->c_in, W, g, nullptr, st));
     in = g;
+  } else if (fused) {
+    CHK(bbh_fused_forward(m, nullptr, nullptr, x, n, W, wsb + b.gap, logits, st));
+    return GW_OK;
   }
   int L = W;
   const float* P = m->params;

@@ -167,6 +167,26 @@ hipError_t launch_cache_layer(const CacheItem* items, int n, const void* arena, 
 hipError_t launch_cache_emit(const CacheItem* items, int n, int W, int max_s, size_t off_noise, const float* strain,
                              float* noise, float* clean, hipStream_t st);
 
+// ---- fused BBHnet (reference shape: 2 -> 32 -> 64 -> 128, k7) ----
+struct BbFusedP {
+  const void* arena;      // pool arena (ring input) or null
+  const Item* items;      // ring descriptors (ring input)
+  const float* x;         // dense input [n][2][W] or null
+  const uint16_t* wa[3];  // packed conv_a fragments per stage
+  const uint16_t* wb[3];  // packed conv_b fragments
+  const uint16_t* ws[3];  // packed 1x1 shortcut fragments
+  const float* ba[3];
+  const float* bb[3];
+  const float* bs[3];
+  const float* hw;        // head weights [128]
+  float* part;            // [n][tiles] pooled-head shares
+  int n, W, tiles;
+};
+
+bool bbh_fused_supported(int c_in, const int* co, int stages);
+int bbh_fused_tiles(int W);  // blocks (pooled-head shares) per window
+hipError_t launch_bbh_fused(const BbFusedP& p, hipStream_t st);
+
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_conv_fp32(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);
 hipError_t launch_conv_bf16(const ConvP& p, bool transposed, int epi, int src, hipStream_t st);

@@ -27,6 +27,7 @@ EXPORTS = [
     "gw_last_error", "gw_pool_init", "gw_pool_free", "gw_stream_open", "gw_stream_close",
     "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
+    "gw_model_set_layerwise",
     "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
     "deepclean_cache_bytes", "gw_stream_attach_cache", "deepclean_cache_bands", "deepclean_forward_cached",
     "deepclean_backward_scratch",
@@ -70,6 +71,7 @@ def lib():
             "gw_model_refresh": ([vp, vp], C.c_int),
             "gw_model_free": ([vp], C.c_int),
             "gw_model_set_cu_budget": ([vp, i32], C.c_int),
+            "gw_model_set_layerwise": ([vp, i32], C.c_int),
             "gw_model_n_params": ([i32, vp, i32, P(i64)], C.c_int),
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
@@ -259,6 +261,11 @@ class _Model:
         """Size the model's persistent kernels for at most ncu compute units
         (0: all), leaving the rest to kernels on other streams."""
         check(lib().gw_model_set_cu_budget(self.h, int(ncu)))
+
+    def set_layerwise(self, on):
+        """BBHnet: per-layer kernels (True) or the fused network kernel (False,
+        the default for the reference shape)."""
+        check(lib().gw_model_set_layerwise(self.h, 1 if on else 0))
 
     def free(self):
         if getattr(self, "h", None) is not None:
