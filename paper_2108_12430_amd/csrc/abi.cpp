@@ -511,6 +511,8 @@ struct LayerD {
   size_t scale, shift;        // packed byte offsets
   size_t wbf;                 // packed bf16 weights byte offset
   size_t wbf_lo;              // packed low bf16 terms (training variant's split operands)
+  size_t wdg, wdg_lo;         // split bf16 packs of the input-gradient (adjoint) convolution
+  bool dg_mfma;               // the adjoint convolution has a matrix-core kernel
   size_t wf16;                // packed fp16 weights byte offset (fused-shape networks)
   size_t wfs, wfs16;          // the fused kernel's own fragment layout (bf16, fp16), where it differs
   bool bf16;                  // BF16 kernel available
@@ -602,6 +604,17 @@ int build_layout(int32_t kind, const int32_t* desc, int32_t len, gw_model& m) {
         ly.wbf = pk;
         pk += eb;
         ly.wbf_lo = pk;
+        pk += eb;
+      }
+      // the adjoint of a stride-2 conv is a stride-2 transposed conv and
+      // vice versa, with input and output channels exchanged
+      const bool conv = ly.type == GW_LAYER_CONV;
+      ly.dg_mfma = ly.s == 2 && gw::conv_bf16_supported(ly.co, ly.ci, ly.k, 2, conv);
+      if (ly.dg_mfma) {
+        const size_t eb = r256(2 * gw::conv_bf16_packed_elems(ly.co, ly.ci, ly.k, conv));
+        ly.wdg = pk;
+        pk += eb;
+        ly.wdg_lo = pk;
         pk += eb;
       }
       m.bf16_all = m.bf16_all && ly.bf16;
@@ -709,6 +722,13 @@ int pack_model(gw_model* m, hipStream_t st) {
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st));
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wbf_lo), ly.ci,
                                     ly.co, ly.k, ly.type == GW_LAYER_CONVT, st, gw::PACK_BF16_LO));
+      }
+      if (ly.dg_mfma) {
+        const bool conv = ly.type == GW_LAYER_CONV;
+        HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wdg), ly.co, ly.ci, ly.k,
+                                    conv, st));
+        HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wdg_lo), ly.co, ly.ci,
+                                    ly.k, conv, st, gw::PACK_BF16_LO));
       }
       if (m->fused) {
         HIPCHK(gw::launch_pack_bf16(P + ly.w, reinterpret_cast<uint16_t*>(m->packed + ly.wf16), ly.ci,
@@ -1538,6 +1558,9 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
     }
     return GW_OK;
   };
+  // running-statistics entries and the biases of normalised layers have
+  // zero gradient; every other entry is written below
+  LAUNCH("zero", st, gw::launch_zero_floats(dparams, m->n_params, st));
   const float* g = dnoise;
   int gi = 0;
   for (int l = L - 1; l >= 0; --l) {
@@ -1554,11 +1577,13 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
                                          m->params + ly.g, n, ly.co, lout[l], partial,
                                          gw::red_chunks(n, lout[l]), dzb, dparams + ly.g,
                                          dparams + ly.be, st));
-      LAUNCH("zero", st, gw::launch_zero_floats(dparams + ly.m, 2 * ly.co, st));
       dz = dzb;
     }
-    LAUNCH(nm("bias_grad", "L", l), st, gw::launch_channel_sum(dz, n, ly.co, lout[l], partial, gw::red_chunks(n, lout[l]),
-                                  dparams + ly.b, st));
+    // a conv bias followed by batch-statistics normalisation has an exactly
+    // zero gradient (the batch mean removes it): left at the initial zero
+    if (!ly.bn)
+      LAUNCH(nm("bias_grad", "L", l), st, gw::launch_channel_sum(dz, n, ly.co, lout[l], partial,
+                                                                  gw::red_chunks(n, lout[l]), dparams + ly.b, st));
     if (ly.type == GW_LAYER_CONV)
       LAUNCH(nm("wgrad", "L", l), st, gw::launch_wgrad(dz, ly.co, lout[l], a_in, ly.ci, lin[l], n, ly.k, ly.s, ly.p, sc + b.wg,
                               dparams + ly.w, st));
@@ -1582,7 +1607,13 @@ extern "C" int deepclean_backward(const gw_model* m, int32_t n, int32_t W, const
     float* gout = scf(b.g[gi]);
     gi ^= 1;
     p.y = gout;
-    if (ly.type == GW_LAYER_CONV) {
+    if (precision == GW_BF16 && ly.dg_mfma) {
+      // split BF16 operands on the matrix cores (as the forward convolutions)
+      p.wpk = reinterpret_cast<const uint16_t*>(m->packed + ly.wdg);
+      p.wpk_lo = reinterpret_cast<const uint16_t*>(m->packed + ly.wdg_lo);
+      LAUNCH(nm("dgrad_bf16", "L", l), st,
+             gw::launch_conv_bf16(p, ly.type == GW_LAYER_CONV, gw::EPI_BIAS, gw::SRC_DENSE, st));
+    } else if (ly.type == GW_LAYER_CONV) {
       p.wsi = (int64_t)ly.ci * ly.k;  // transposed kernel reads w[i*wsi + o*wso + j], i = conv out ch
       p.wso = ly.k;
       LAUNCH(nm("dgrad", "L", l), st, gw::launch_conv_fp32(p, true, gw::EPI_BIAS, gw::SRC_DENSE, st));
@@ -1622,7 +1653,7 @@ extern "C" int gw_bandpass_workspace(int32_t n, int32_t W, float fs, float f_lo,
   if (!bytes || n < 1) return fail(GW_EINVAL, "bad argument");
   int lo, hi;
   CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
-  *bytes = r256((size_t)n * (hi - lo + 1) * 2 * sizeof(float));
+  *bytes = r256(gw::bandpass_ws_floats(n, W, hi - lo + 1) * sizeof(float));
   return GW_OK;
 }
 
@@ -1632,7 +1663,8 @@ extern "C" int gw_bandpass_mse(int32_t n, int32_t W, float fs, float f_lo, float
   if (n < 1 || !strain || !noise || !ws || (!loss && !dnoise)) return fail(GW_EINVAL, "bad argument");
   int lo, hi;
   CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
-  if (ws_bytes < (size_t)n * (hi - lo + 1) * 2 * sizeof(float)) return fail(GW_EINVAL, "workspace too small");
+  if (ws_bytes < gw::bandpass_ws_floats(n, W, hi - lo + 1) * sizeof(float))
+    return fail(GW_EINVAL, "workspace too small");
   LAUNCH("bandpass", S(hip_stream), gw::launch_bandpass(n, W, lo, hi, strain, noise, reinterpret_cast<float*>(ws), loss, dnoise,
                              S(hip_stream)));
   return GW_OK;
@@ -1683,7 +1715,7 @@ extern "C" int gw_bandpass_mse_noalloc(int32_t n, int32_t W, float fs, float f_l
   if (n < 1 || !strain || !noise || (!loss && !dnoise)) return fail(GW_EINVAL, "bad argument");
   int lo, hi;
   CHK(band(W, fs, f_lo, f_hi, &lo, &hi));
-  const size_t need = (size_t)n * (hi - lo + 1) * 2 * sizeof(float);
+  const size_t need = gw::bandpass_ws_floats(n, W, hi - lo + 1) * sizeof(float);
   if (need > kNoAllocScratchBytes)
     return fail(GW_EINVAL, "n x band bins = " + std::to_string((size_t)n * (hi - lo + 1)) +
                                " exceeds the no-allocation scratch limit of " +

@@ -250,6 +250,8 @@ size_t wgrad_scratch_bytes(int n, int Lp, int nw);
 // LDS per block: 4*(Ca*64 + Cc*(stride*63 + k)) bytes, must be <= 64 KiB.
 hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, int Lq, int n,
                         int k, int stride, int pad, void* scratch, float* dw, hipStream_t st);
+// workspace of the band-passed loss: the n x nb (cos, sin) projections
+size_t bandpass_ws_floats(int n, int W, int nb);
 hipError_t launch_bandpass(int n, int W, int k_lo, int k_hi, const float* strain,
                            const float* noise, float* proj, float* loss, float* dnoise,
                            hipStream_t st);

@@ -6,6 +6,8 @@
 // depend on scheduling.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace gw {
 
 static constexpr int RCHUNK = 4096;  // (batch, time) elements per reduction chunk
@@ -205,61 +207,114 @@ hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* 
 // Weight gradient: dw[a][c][j] = sum_b sum_t P[b][a][t] * Q[b][c][s t - p + j]
 // (Q zero outside [0, Lq)).  For a conv layer P = dL/dz (a = out channel) and
 // Q = layer input; for a transposed layer P = layer input and Q = dL/dz.
-// Stage 1: one block per (batch item, 64-step time chunk of P) stages the
-// chunk of P and the matching window of Q in LDS and writes FP32 partials.
-// Stages 2 and 3 add the partials of every weight in a fixed two-level tree
-// (groups of 64 chunks, then the groups) in FP64.
+// Stage 1, a split-K GEMM on the matrix cores: D[a][n] (n = c k + j) summed
+// over K = (batch item, time).  Block g walks a fixed run of chunks (batch
+// item, 64 time steps) in order; per chunk it stages the chunk of P and the
+// matching window of Q in LDS (FP32) and runs v_mfma_f32_16x16x4_f32 (exact
+// FP32 products, FP32 accumulation) over 16 K steps of 4 time steps; its
+// accumulators stay in registers across its chunks and are written once as
+// block g's FP32 partial.  Stages 2 and 3 add the partials of every weight in
+// a fixed two-level tree (groups of 64 partials, then the groups) in FP64.
 // ---------------------------------------------------------------------------
-static constexpr int WT = 64;
-static constexpr int WG = 64;
+static constexpr int WT = 64;   // time steps per chunk
+static constexpr int WG = 64;   // partials per group of the reduction tree
+static constexpr int WPS = WT + 1;  // LDS row stride of the P chunk (odd: no bank conflicts down a column)
+static constexpr int WNW = 8;       // waves per block
+static constexpr int WTPW = 7;      // most accumulator tiles per wave
 
 int wgrad_chunks(int n, int Lp) { return n * ((Lp + WT - 1) / WT); }
 
+// blocks (= partials) of stage 1: enough to fill the chip, few enough that
+// the partials of a large layer stay near 16 MB
+static int wgrad_blocks(int n, int Lp, int nw) {
+  const int nchunk = wgrad_chunks(n, Lp);
+  const int cap = std::max(256, (int)std::min<int64_t>(1024, ((int64_t)4 << 20) / std::max(nw, 1)));
+  return std::max(1, std::min(nchunk, cap));
+}
+
 size_t wgrad_scratch_bytes(int n, int Lp, int nw) {
-  const size_t nchunk = (size_t)wgrad_chunks(n, Lp);
-  const size_t ngroup = (nchunk + WG - 1) / WG;
-  size_t a = ((nchunk * nw * sizeof(float)) + 255) & ~(size_t)255;
+  const size_t G = (size_t)wgrad_blocks(n, Lp, nw);
+  const size_t ngroup = (G + WG - 1) / WG;
+  size_t a = ((G * nw * sizeof(float)) + 255) & ~(size_t)255;
   return a + ngroup * nw * sizeof(double);
 }
 
 struct WgP {
   const float* P;
   const float* Q;
-  int Ca, Lp, Cc, Lq, n, k, s, pad, tchunks;
-  float* partial;  // [nchunk][Ca*Cc*k]
+  int Ca, Lp, Cc, Lq, n, k, s, pad, tchunks, nchunk;
+  float* partial;  // [blocks][Ca*Cc*k]
 };
 
-__global__ __launch_bounds__(256) void wgrad_partial(WgP p) {
+typedef float wf32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64 * WNW, 2) void wgrad_partial(WgP p) {
   extern __shared__ float lds[];
-  const int chunk = blockIdx.x;
-  const int b = chunk / p.tchunks, t0 = (chunk % p.tchunks) * WT;
   const int span = p.s * (WT - 1) + p.k;  // Q samples touched by one chunk
-  float* Ps = lds;                        // [Ca][WT]
-  float* Qs = lds + p.Ca * WT;            // [Cc][span]
-  const float* Pb = p.P + (int64_t)b * p.Ca * p.Lp;
-  const float* Qb = p.Q + (int64_t)b * p.Cc * p.Lq;
-  for (int e = threadIdx.x; e < p.Ca * WT; e += 256) {
-    const int a = e / WT, t = e - a * WT;
-    Ps[e] = (t0 + t < p.Lp) ? Pb[(int64_t)a * p.Lp + t0 + t] : 0.0f;
+  float* Ps = lds;                        // [Ca][WPS]
+  float* Qs = lds + p.Ca * WPS;           // [Cc][span]
+  const int nk = p.Cc * p.k;              // GEMM columns
+  const int MTa = (p.Ca + 15) / 16, NTn = (nk + 15) / 16, ntile = MTa * NTn;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  // this lane's LDS offsets for each of its tiles (tile u of the wave is
+  // wave + WNW u): A row a = 16 mt + lr, B column n = 16 nt + lr = (c, j)
+  int aoff[WTPW], boff[WTPW];
+#pragma unroll
+  for (int u = 0; u < WTPW; ++u) {
+    const int tile = wave + WNW * u;
+    const int mt = tile / NTn, nt = tile - mt * NTn;
+    const int a = 16 * mt + lr, nn = 16 * nt + lr;
+    aoff[u] = (tile < ntile && a < p.Ca) ? a * WPS : -1;
+    boff[u] = (tile < ntile && nn < nk) ? (nn / p.k) * span + (nn % p.k) : -1;
   }
-  const int q0 = p.s * t0 - p.pad;
-  for (int e = threadIdx.x; e < p.Cc * span; e += 256) {
-    const int c = e / span, u = e - c * span;
-    const int q = q0 + u;
-    Qs[e] = (q >= 0 && q < p.Lq) ? Qb[(int64_t)c * p.Lq + q] : 0.0f;
+  wf32x4 acc[WTPW];
+#pragma unroll
+  for (int u = 0; u < WTPW; ++u) acc[u] = wf32x4{0.f, 0.f, 0.f, 0.f};
+  const int G = gridDim.x;
+  const int c0 = (int)((int64_t)p.nchunk * blockIdx.x / G), c1 = (int)((int64_t)p.nchunk * (blockIdx.x + 1) / G);
+  for (int chunk = c0; chunk < c1; ++chunk) {
+    const int b = chunk / p.tchunks, t0 = (chunk % p.tchunks) * WT;
+    const float* Pb = p.P + (int64_t)b * p.Ca * p.Lp;
+    const float* Qb = p.Q + (int64_t)b * p.Cc * p.Lq;
+    __syncthreads();  // the previous chunk's reads are done
+    for (int e = threadIdx.x; e < p.Ca * WT; e += 64 * WNW) {
+      const int a = e / WT, t = e - a * WT;
+      Ps[a * WPS + t] = (t0 + t < p.Lp) ? Pb[(int64_t)a * p.Lp + t0 + t] : 0.0f;
+    }
+    const int q0 = p.s * t0 - p.pad;
+    for (int e = threadIdx.x; e < p.Cc * span; e += 64 * WNW) {
+      const int c = e / span, u = e - c * span;
+      const int q = q0 + u;
+      Qs[e] = (q >= 0 && q < p.Lq) ? Qb[(int64_t)c * p.Lq + q] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < WT / 4; ++kk) {
+      const int t = 4 * kk + lk;  // this lane's K index
+#pragma unroll
+      for (int u = 0; u < WTPW; ++u) {
+        if (wave + WNW * u >= ntile) break;  // wave-uniform
+        const float av = aoff[u] >= 0 ? Ps[aoff[u] + t] : 0.0f;
+        const float bv = boff[u] >= 0 ? Qs[boff[u] + p.s * t] : 0.0f;
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[u], 0, 0, 0);
+      }
+    }
   }
-  __syncthreads();
-  const int nw = p.Ca * p.Cc * p.k;
-  float* out = p.partial + (int64_t)chunk * nw;
-  for (int e = threadIdx.x; e < nw; e += 256) {
-    const int a = e / (p.Cc * p.k);
-    const int rem = e - a * p.Cc * p.k;
-    const int c = rem / p.k, j = rem - c * p.k;
-    const float* pr = Ps + a * WT;
-    const float* qr = Qs + c * span + j;
-    float acc = 0.0f;
-    for (int t = 0; t < WT; ++t) acc = fmaf(pr[t], qr[p.s * t], acc);
-    out[e] = acc;
+  // D[row = 4 lk + r][col = lr] of tile u: weight (a, n)
+  const int nw = p.Ca * nk;
+  float* out = p.partial + (int64_t)blockIdx.x * nw;
+#pragma unroll
+  for (int u = 0; u < WTPW; ++u) {
+    const int tile = wave + WNW * u;
+    if (tile >= ntile) break;
+    const int mt = tile / NTn, nt = tile - mt * NTn;
+    const int nn = 16 * nt + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 16 * mt + 4 * lk + r;
+      if (a < p.Ca && nn < nk) out[(int64_t)a * nk + nn] = acc[u][r];
+    }
   }
 }
 
@@ -297,18 +352,20 @@ hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, 
   p.s = stride;
   p.pad = pad;
   p.tchunks = (Lp + WT - 1) / WT;
-  const int nchunk = wgrad_chunks(n, Lp);
+  p.nchunk = wgrad_chunks(n, Lp);
   const int nw = Ca * Cc * k;
-  const int ngroup = (nchunk + WG - 1) / WG;
+  const int G = wgrad_blocks(n, Lp, nw);
+  const int ngroup = (G + WG - 1) / WG;
   p.partial = reinterpret_cast<float*>(scratch);
   double* mid = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) +
-                                          ((((size_t)nchunk * nw * sizeof(float)) + 255) & ~(size_t)255));
+                                          ((((size_t)G * nw * sizeof(float)) + 255) & ~(size_t)255));
   const int span = stride * (WT - 1) + k;
-  const size_t lds = sizeof(float) * ((size_t)Ca * WT + (size_t)Cc * span);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(wgrad_partial, dim3(nchunk), dim3(256), lds, st, p);
+  const size_t lds = sizeof(float) * ((size_t)Ca * WPS + (size_t)Cc * span);
+  // every accumulator tile of the GEMM must have a register slot in its wave
+  if (lds > 64 * 1024 || ((Ca + 15) / 16) * ((Cc * k + 15) / 16) > WNW * WTPW) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wgrad_partial, dim3(G), dim3(64 * WNW), lds, st, p);
   hipLaunchKernelGGL(wgrad_group, dim3((nw + 255) / 256, ngroup), dim3(256), 0, st, p.partial,
-                     nchunk, nw, mid);
+                     G, nw, mid);
   hipLaunchKernelGGL(wgrad_final, dim3((nw + 255) / 256), dim3(256), 0, st, mid, ngroup, nw, dw);
   return hipGetLastError();
 }
@@ -319,7 +376,9 @@ hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, 
 //   ||P r||^2 = sum_k c_k (A_k^2 + B_k^2),  A_k = <r, cos_k>, B_k = <r, sin_k>,
 //   P r[t]    = sum_k c_k (A_k cos_k[t] + B_k sin_k[t]),
 // with c_k = 2/W (c_k = 1/W for k = 0 or k = W/2).  Angles are reduced
-// exactly in integers, (k t mod W), before the sin/cos evaluation.
+// exactly in integers, m = (k t mod W), before the sin/cos evaluation; the
+// index advances by a constant per step (one compare and subtract) instead
+// of a 64-bit division per sample.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void bp_project(const float* strain, const float* noise, int W,
                                                   int k_lo, float* proj) {
@@ -328,13 +387,17 @@ __global__ __launch_bounds__(256) void bp_project(const float* strain, const flo
   const float* nr = noise + (int64_t)b * W;
   double sa = 0.0, sb = 0.0;
   const float twoW = 2.0f / (float)W;
+  // m = k t mod W for t = threadIdx.x, threadIdx.x + 256, ...
+  int m = (int)(((int64_t)k * threadIdx.x) % W);
+  const int step = (int)(((int64_t)k * 256) % W);
   for (int t = threadIdx.x; t < W; t += 256) {
     const float r = sr[t] - nr[t];
-    const int64_t m = ((int64_t)k * t) % W;
     float sn, cs;
     sincospif(twoW * (float)m, &sn, &cs);
     sa += (double)(r * cs);
     sb += (double)(r * sn);
+    m += step;
+    if (m >= W) m -= W;
   }
   block_sum2(sa, sb);
   if (threadIdx.x == 0) {
@@ -366,15 +429,23 @@ __global__ __launch_bounds__(256) void bp_grad(const float* proj, int nb, int W,
   if (t >= W) return;
   const float* pr = proj + (int64_t)b * nb * 2;
   const float twoW = 2.0f / (float)W;
+  // m = k t mod W for k = k_lo, k_lo + 1, ...: advances by t each bin
+  int m = (int)(((int64_t)k_lo * t) % W);
   float acc = 0.0f;
   for (int kk = 0; kk < nb; ++kk) {
     const int k = k_lo + kk;
-    const int64_t m = ((int64_t)k * t) % W;
     float sn, cs;
     sincospif(twoW * (float)m, &sn, &cs);
     acc = fmaf(bin_weight(k, W), fmaf(pr[2 * kk], cs, pr[2 * kk + 1] * sn), acc);
+    m += t;
+    if (m >= W) m -= W;
   }
   dnoise[(int64_t)b * W + t] = scale * acc;
+}
+
+size_t bandpass_ws_floats(int n, int W, int nb) {
+  (void)W;
+  return (size_t)n * nb * 2;
 }
 
 hipError_t launch_bandpass(int n, int W, int k_lo, int k_hi, const float* strain,
