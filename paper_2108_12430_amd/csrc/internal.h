@@ -245,7 +245,6 @@ hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* 
                                    float* dgamma, float* dbeta, hipStream_t st);
 hipError_t launch_channel_sum(const float* x, int n, int C, int L, double* partial, int nchunk,
                               float* out, hipStream_t st);
-int wgrad_chunks(int n, int Lp);
 size_t wgrad_scratch_bytes(int n, int Lp, int nw);
 // LDS per block: 4*(Ca*64 + Cc*(stride*63 + k)) bytes, must be <= 64 KiB.
 hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, int Lq, int n,

@@ -7,6 +7,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <initializer_list>
 
 namespace gw {
 
@@ -54,23 +55,46 @@ __global__ __launch_bounds__(256) void chan_partial(RedP p) {
     mu = p.mean[c];
     is = p.invstd[c];
   }
-  for (int r = 0; r < RCHUNK / 256; ++r) {
-    const int64_t e = (int64_t)q * RCHUNK + r * 256 + threadIdx.x;
-    if (e >= N) break;
-    const int64_t b = e / p.L, t = e - b * p.L;
-    const int64_t idx = (b * p.C + c) * p.L + t;
+  // this thread's elements e = q RCHUNK + 256 r + tid, (b, t) = (e / L, e % L)
+  // tracked incrementally; all loads are issued before the in-order sums
+  constexpr int NR = RCHUNK / 256;
+  const int64_t e0 = (int64_t)q * RCHUNK + threadIdx.x;
+  const int nr = (int)std::max<int64_t>(0, std::min<int64_t>(NR, (N - e0 + 255) / 256));
+  int64_t b = e0 / p.L;
+  int t = (int)(e0 - b * p.L);
+  int64_t idx[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    idx[r] = r < nr ? (b * p.C + c) * p.L + t : 0;
+    t += 256;
+    while (t >= p.L) {
+      t -= p.L;
+      ++b;
+    }
+  }
+  float xv[NR], av[MODE == R_BNBWD ? NR : 1], zv[MODE == R_BNBWD ? NR : 1];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    xv[r] = p.x[idx[r]];
+    if (MODE == R_BNBWD) {
+      av[r] = p.a[idx[r]];
+      zv[r] = p.z[idx[r]];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) break;
     if (MODE == R_STATS) {
-      const double v = p.x[idx];
+      const double v = xv[r];
       s0 += v;
       s1 += v * v;
     } else if (MODE == R_BNBWD) {
-      const float av = p.a[idx];
-      const float dh = p.x[idx] * (1.0f - av * av);
-      const float xh = (p.z[idx] - mu) * is;
+      const float dh = xv[r] * (1.0f - av[r] * av[r]);
+      const float xh = (zv[r] - mu) * is;
       s0 += (double)dh;
       s1 += (double)dh * (double)xh;
     } else {
-      s0 += (double)p.x[idx];
+      s0 += (double)xv[r];
     }
   }
   block_sum2(s0, s1);
@@ -142,40 +166,99 @@ hipError_t launch_channel_sum(const float* x, int n, int C, int L, double* parti
   return hipGetLastError();
 }
 
+// Elementwise kernels over [n][C][L]: grid y = rows (b C + c, strided by
+// gridDim.y), x = runs of 1024 positions; 4 positions per thread, as one
+// float4 when every row starts 16-byte aligned.
+static inline bool rows_vec4(int L, std::initializer_list<const void*> ptrs) {
+  if (L % 4) return false;
+  for (const void* q : ptrs)
+    if (reinterpret_cast<uintptr_t>(q) % 16) return false;
+  return true;
+}
+
+static inline dim3 rows_grid(int n, int C, int L) {
+  const int64_t rows = (int64_t)n * C;
+  return dim3((unsigned)((L + 1023) / 1024), (unsigned)std::min<int64_t>(rows, 65535));
+}
+
 // a = tanh(gamma (z - mean) invstd + beta)
+template <bool V4>
 __global__ __launch_bounds__(256) void bn_apply_tanh_kernel(const float* z, const float* mean,
                                                             const float* invstd, const float* gamma,
                                                             const float* beta, float* a, int C,
-                                                            int L, int64_t total) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  const int c = (int)((e / L) % C);
-  a[e] = tanhf(fmaf(gamma[c], (z[e] - mean[c]) * invstd[c], beta[c]));
+                                                            int L, int64_t rows) {
+  const int t = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (t >= L) return;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int c = (int)(row % C);
+    const float m = mean[c], is = invstd[c], g = gamma[c], be = beta[c];
+    const float* zr = z + row * L + t;
+    float* ar = a + row * L + t;
+    if (V4) {
+      const float4 v = *reinterpret_cast<const float4*>(zr);
+      float4 r;
+      r.x = tanhf(fmaf(g, (v.x - m) * is, be));
+      r.y = tanhf(fmaf(g, (v.y - m) * is, be));
+      r.z = tanhf(fmaf(g, (v.z - m) * is, be));
+      r.w = tanhf(fmaf(g, (v.w - m) * is, be));
+      *reinterpret_cast<float4*>(ar) = r;
+    } else {
+      for (int j = 0; j < 4 && t + j < L; ++j) ar[j] = tanhf(fmaf(g, (zr[j] - m) * is, be));
+    }
+  }
 }
 
 hipError_t launch_bn_apply_tanh(const float* z, const float* mean, const float* invstd,
                                 const float* gamma, const float* beta, float* a, int n, int C,
                                 int L, hipStream_t st) {
-  const int64_t total = (int64_t)n * C * L;
-  hipLaunchKernelGGL(bn_apply_tanh_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     z, mean, invstd, gamma, beta, a, C, L, total);
+  const int64_t rows = (int64_t)n * C;
+  if (rows < 1 || L < 1) return hipSuccess;
+  if (rows_vec4(L, {z, a}))
+    hipLaunchKernelGGL(bn_apply_tanh_kernel<true>, rows_grid(n, C, L), dim3(256), 0, st, z, mean, invstd, gamma,
+                       beta, a, C, L, rows);
+  else
+    hipLaunchKernelGGL(bn_apply_tanh_kernel<false>, rows_grid(n, C, L), dim3(256), 0, st, z, mean, invstd, gamma,
+                       beta, a, C, L, rows);
   return hipGetLastError();
 }
 
 // dz = gamma invstd (dh - sum(dh)/N - xhat sum(dh xhat)/N), dh = g (1 - a^2)
+__device__ __forceinline__ float bn_tanh_bwd_one(float g, float av, float zv, float m, float is, float gis,
+                                                 float s1, float s2) {
+  const float dh = g * (1.0f - av * av);
+  const float xh = (zv - m) * is;
+  return gis * (dh - s1 - xh * s2);
+}
+
+template <bool V4>
 __global__ __launch_bounds__(256) void bn_tanh_bwd_kernel(const float* g, const float* a,
                                                           const float* z, const float* mean,
                                                           const float* invstd, const float* gamma,
                                                           const float* sdh, const float* sdhx,
-                                                          float* dz, int C, int L, int64_t total,
+                                                          float* dz, int C, int L, int64_t rows,
                                                           float invN) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  const int c = (int)((e / L) % C);
-  const float av = a[e];
-  const float dh = g[e] * (1.0f - av * av);
-  const float xh = (z[e] - mean[c]) * invstd[c];
-  dz[e] = gamma[c] * invstd[c] * (dh - sdh[c] * invN - xh * (sdhx[c] * invN));
+  const int t = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (t >= L) return;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int c = (int)(row % C);
+    const float m = mean[c], is = invstd[c], gis = gamma[c] * invstd[c];
+    const float s1 = sdh[c] * invN, s2 = sdhx[c] * invN;
+    const int64_t o = row * L + t;
+    if (V4) {
+      const float4 gv = *reinterpret_cast<const float4*>(g + o);
+      const float4 av = *reinterpret_cast<const float4*>(a + o);
+      const float4 zv = *reinterpret_cast<const float4*>(z + o);
+      float4 r;
+      r.x = bn_tanh_bwd_one(gv.x, av.x, zv.x, m, is, gis, s1, s2);
+      r.y = bn_tanh_bwd_one(gv.y, av.y, zv.y, m, is, gis, s1, s2);
+      r.z = bn_tanh_bwd_one(gv.z, av.z, zv.z, m, is, gis, s1, s2);
+      r.w = bn_tanh_bwd_one(gv.w, av.w, zv.w, m, is, gis, s1, s2);
+      *reinterpret_cast<float4*>(dz + o) = r;
+    } else {
+      for (int j = 0; j < 4 && t + j < L; ++j)
+        dz[o + j] = bn_tanh_bwd_one(g[o + j], a[o + j], z[o + j], m, is, gis, s1, s2);
+    }
+  }
 }
 
 hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* z,
@@ -196,10 +279,14 @@ hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* 
   hipLaunchKernelGGL(chan_partial<R_BNBWD>, dim3(nchunk, C), dim3(256), 0, st, p);
   hipLaunchKernelGGL(chan_final<R_BNBWD>, dim3(C), dim3(256), 0, st, partial, nchunk,
                      (int64_t)n * L, dbeta, dgamma);
-  const int64_t total = (int64_t)n * C * L;
-  hipLaunchKernelGGL(bn_tanh_bwd_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
-                     a, z, mean, invstd, gamma, dbeta, dgamma, dz, C, L, total,
-                     (float)(1.0 / ((double)n * L)));
+  const int64_t rows = (int64_t)n * C;
+  const float invN = (float)(1.0 / ((double)n * L));
+  if (rows_vec4(L, {g, a, z, dz}))
+    hipLaunchKernelGGL(bn_tanh_bwd_kernel<true>, rows_grid(n, C, L), dim3(256), 0, st, g, a, z, mean, invstd, gamma,
+                       dbeta, dgamma, dz, C, L, rows, invN);
+  else
+    hipLaunchKernelGGL(bn_tanh_bwd_kernel<false>, rows_grid(n, C, L), dim3(256), 0, st, g, a, z, mean, invstd, gamma,
+                       dbeta, dgamma, dz, C, L, rows, invN);
   return hipGetLastError();
 }
 
@@ -209,31 +296,68 @@ hipError_t launch_bn_tanh_backward(const float* g, const float* a, const float* 
 // Q = layer input; for a transposed layer P = layer input and Q = dL/dz.
 // Stage 1, a split-K GEMM on the matrix cores: D[a][n] (n = c k + j) summed
 // over K = (batch item, time).  Block g walks a fixed run of chunks (batch
-// item, 64 time steps) in order; per chunk it stages the chunk of P and the
-// matching window of Q in LDS (FP32) and runs v_mfma_f32_16x16x4_f32 (exact
-// FP32 products, FP32 accumulation) over 16 K steps of 4 time steps; its
-// accumulators stay in registers across its chunks and are written once as
-// block g's FP32 partial.  Stages 2 and 3 add the partials of every weight in
-// a fixed two-level tree (groups of 64 partials, then the groups) in FP64.
+// item, WT time steps) in order.  Each thread loads its share of a chunk (P
+// rows and the matching window of Q) into registers in one batch of
+// independent loads, and the next chunk's loads are issued before the current
+// chunk's MFMAs, so memory latency overlaps compute.  The staged chunk sits in
+// LDS (FP32) and v_mfma_f32_16x16x4_f32 (exact FP32 products, FP32
+// accumulation) runs over WT / 4 K steps of 4 time steps.  Layers with fewer
+// accumulator tiles than waves split each chunk's K steps between wave
+// groups, whose accumulators are added in a fixed order at the end.  The
+// block's sums are written once as block g's FP32 partial.  Stages 2 and 3 add
+// the partials of every weight in a fixed two-level tree (groups of 64
+// partials, then the groups) in FP64.  Every order is fixed: the result is
+// deterministic.
 // ---------------------------------------------------------------------------
-static constexpr int WT = 64;   // time steps per chunk
-static constexpr int WG = 64;   // partials per group of the reduction tree
-static constexpr int WPS = WT + 1;  // LDS row stride of the P chunk (odd: no bank conflicts down a column)
-static constexpr int WNW = 8;       // waves per block
-static constexpr int WTPW = 7;      // most accumulator tiles per wave
+static constexpr int WG = 64;    // partials per group of the reduction tree
+static constexpr int WNW = 8;    // waves per block
+static constexpr int WTH = 64 * WNW;
+static constexpr int WTPW = 7;   // most accumulator tiles per wave
 
-int wgrad_chunks(int n, int Lp) { return n * ((Lp + WT - 1) / WT); }
+// chunk configurations, largest chunk first: time steps, the most P and Q
+// elements one thread stages per chunk, the most accumulator tiles per wave
+struct WgCfg {
+  int wt, pmax, qmax, ntmax;
+};
+static constexpr WgCfg kWgCfg[] = {{1024, 8, 24, 3}, {512, 8, 24, 3}, {256, 8, 24, 3},
+                                   {128, 8, 12, 3},  {64, 8, 12, 7},  {64, 16, 24, 7}};
 
-// blocks (= partials) of stage 1: enough to fill the chip, few enough that
-// the partials of a large layer stay near 16 MB
-static int wgrad_blocks(int n, int Lp, int nw) {
-  const int nchunk = wgrad_chunks(n, Lp);
-  const int cap = std::max(256, (int)std::min<int64_t>(1024, ((int64_t)4 << 20) / std::max(nw, 1)));
-  return std::max(1, std::min(nchunk, cap));
+static int wgrad_qs(int span) { return span + ((16 - span % 64) + 64) % 64; }  // row stride = 16 mod 64 banks
+
+static size_t wgrad_lds(int Ca, int Cc, int k, int s, int wt) {
+  const size_t need = sizeof(float) * ((size_t)(Ca + 1) * (wt + 4) + (size_t)(Cc + 1) * wgrad_qs(s * (wt - 1) + k) + WTH);
+  return std::max(need, sizeof(float) * 8 * 256);  // room to combine the wave groups' accumulators
 }
 
+// wave groups splitting a chunk's K steps: as many as the idle waves allow
+// (ntile accumulator tiles, ksp * ntile <= 8 when ntile < 8)
+__host__ __device__ inline int wgrad_ksp(int ntile) {
+  return ntile >= WNW ? 1 : (2 * ntile > WNW ? 1 : (4 * ntile > WNW ? 2 : (8 * ntile > WNW ? 4 : 8)));
+}
+
+// the configuration a layer runs with (index into kWgCfg), -1 if none fits
+static int wgrad_cfg(int Ca, int Cc, int k, int s) {
+  const int ntile = ((Ca + 15) / 16) * ((Cc * k + 15) / 16);
+  const int nwk = WNW / wgrad_ksp(ntile), tpw = (ntile + nwk - 1) / nwk;
+  for (int i = 0; i < (int)(sizeof(kWgCfg) / sizeof(kWgCfg[0])); ++i) {
+    const WgCfg c = kWgCfg[i];
+    const int span = s * (c.wt - 1) + k;
+    if (Ca * c.wt <= WTH * c.pmax && Cc * span <= WTH * c.qmax && span < 65536 && tpw <= c.ntmax &&
+        wgrad_lds(Ca, Cc, k, s, c.wt) <= 64 * 1024)
+      return i;
+  }
+  return -1;
+}
+
+static int wgrad_chunks(int n, int Lp, int wt) { return n * ((Lp + wt - 1) / wt); }
+
+// blocks (= partials) of stage 1: one resident round, one 8-wave block per CU
+// (the staging registers and the accumulators take up to 256 VGPRs)
+static int wgrad_blocks(int nchunk) { return std::max(1, std::min(nchunk, 256)); }
+
+// an upper bound over every configuration (the smallest chunk has the most)
 size_t wgrad_scratch_bytes(int n, int Lp, int nw) {
-  const size_t G = (size_t)wgrad_blocks(n, Lp, nw);
+  const size_t G = (size_t)wgrad_blocks(wgrad_chunks(n, Lp, 64));
   const size_t ngroup = (G + WG - 1) / WG;
   size_t a = ((G * nw * sizeof(float)) + 255) & ~(size_t)255;
   return a + ngroup * nw * sizeof(double);
@@ -242,71 +366,171 @@ size_t wgrad_scratch_bytes(int n, int Lp, int nw) {
 struct WgP {
   const float* P;
   const float* Q;
-  int Ca, Lp, Cc, Lq, n, k, s, pad, tchunks, nchunk;
+  int Ca, Lp, Cc, Lq, n, k, s, pad, tchunks, nchunk, qs;
   float* partial;  // [blocks][Ca*Cc*k]
 };
 
 typedef float wf32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(64 * WNW, 2) void wgrad_partial(WgP p) {
-  extern __shared__ float lds[];
-  const int span = p.s * (WT - 1) + p.k;  // Q samples touched by one chunk
-  float* Ps = lds;                        // [Ca][WPS]
-  float* Qs = lds + p.Ca * WPS;           // [Cc][span]
-  const int nk = p.Cc * p.k;              // GEMM columns
-  const int MTa = (p.Ca + 15) / 16, NTn = (nk + 15) / 16, ntile = MTa * NTn;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int lr = lane & 15, lk = lane >> 4;
-  // this lane's LDS offsets for each of its tiles (tile u of the wave is
-  // wave + WNW u): A row a = 16 mt + lr, B column n = 16 nt + lr = (c, j)
-  int aoff[WTPW], boff[WTPW];
+// one chunk's K steps for a wave with NT accumulator tiles: K steps slice,
+// slice + ksp, ... of 4 time steps each; every operand read is unconditional
+// (rows and columns past the GEMM read zero rows)
+template <int NT, int WT>
+__device__ __forceinline__ void wgrad_mma(const float* Ps, const float* Qs, const int* aoff, const int* boff, int s,
+                                          int slice, int ksp, int lk, wf32x4* acc) {
+  const int nkk = WT / 4 / ksp;
+  const float* pa = Ps + 4 * slice + lk;
+  const float* qb = Qs + s * (4 * slice + lk);
+  const int da = 4 * ksp, db = 4 * ksp * s;
+#pragma unroll 4
+  for (int it = 0; it < nkk; ++it) {
 #pragma unroll
-  for (int u = 0; u < WTPW; ++u) {
-    const int tile = wave + WNW * u;
-    const int mt = tile / NTn, nt = tile - mt * NTn;
-    const int a = 16 * mt + lr, nn = 16 * nt + lr;
-    aoff[u] = (tile < ntile && a < p.Ca) ? a * WPS : -1;
-    boff[u] = (tile < ntile && nn < nk) ? (nn / p.k) * span + (nn % p.k) : -1;
+    for (int u = 0; u < NT; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[aoff[u]], qb[boff[u]], acc[u], 0, 0, 0);
+    pa += da;
+    qb += db;
   }
-  wf32x4 acc[WTPW];
+}
+
+template <int WT, int PMAX, int QMAX, int NTMAX>
+__global__ __launch_bounds__(WTH, 2) void wgrad_partial(WgP p) {
+  extern __shared__ float lds[];
+  constexpr int WPS = WT + 4;              // P row stride: rows 4 banks apart
+  const int span = p.s * (WT - 1) + p.k;   // Q samples one chunk touches
+  float* Ps = lds;                         // [Ca + 1][WPS], row Ca zero
+  float* Qs = lds + (p.Ca + 1) * WPS;      // [Cc + 1][qs], row Cc zero
+  const int tid = threadIdx.x;
+  const int np = p.Ca * WT, nq = p.Cc * span;
+  // this thread's Q elements (channel << 16 | position in the span), the
+  // same for every chunk; -1 where the thread has none
+  int qcu[QMAX];
 #pragma unroll
-  for (int u = 0; u < WTPW; ++u) acc[u] = wf32x4{0.f, 0.f, 0.f, 0.f};
-  const int G = gridDim.x;
-  const int c0 = (int)((int64_t)p.nchunk * blockIdx.x / G), c1 = (int)((int64_t)p.nchunk * (blockIdx.x + 1) / G);
-  for (int chunk = c0; chunk < c1; ++chunk) {
-    const int b = chunk / p.tchunks, t0 = (chunk % p.tchunks) * WT;
+  for (int i = 0; i < QMAX; ++i) {
+    const int e = tid + WTH * i;
+    const int c = e / span;
+    qcu[i] = e < nq ? (c << 16) | (e - c * span) : -1;
+  }
+  // loads are unconditional, from addresses clamped into the tensors, so that
+  // a chunk's loads are all in flight together; the staging store zeroes
+  // what lies outside (rows past C, time past L, Q's zero padding)
+  float pv[PMAX], qv[QMAX];
+  auto fetch = [&](int chunk) {
+    const int b = chunk / p.tchunks, t0 = (chunk - b * p.tchunks) * WT;
     const float* Pb = p.P + (int64_t)b * p.Ca * p.Lp;
     const float* Qb = p.Q + (int64_t)b * p.Cc * p.Lq;
-    __syncthreads();  // the previous chunk's reads are done
-    for (int e = threadIdx.x; e < p.Ca * WT; e += 64 * WNW) {
-      const int a = e / WT, t = e - a * WT;
-      Ps[a * WPS + t] = (t0 + t < p.Lp) ? Pb[(int64_t)a * p.Lp + t0 + t] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+      const int e = tid + WTH * i, a = min(e / WT, p.Ca - 1), t = min(t0 + e % WT, p.Lp - 1);
+      pv[i] = Pb[(int64_t)a * p.Lp + t];
     }
     const int q0 = p.s * t0 - p.pad;
-    for (int e = threadIdx.x; e < p.Cc * span; e += 64 * WNW) {
-      const int c = e / span, u = e - c * span;
-      const int q = q0 + u;
-      Qs[e] = (q >= 0 && q < p.Lq) ? Qb[(int64_t)c * p.Lq + q] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < WT / 4; ++kk) {
-      const int t = 4 * kk + lk;  // this lane's K index
 #pragma unroll
-      for (int u = 0; u < WTPW; ++u) {
-        if (wave + WNW * u >= ntile) break;  // wave-uniform
-        const float av = aoff[u] >= 0 ? Ps[aoff[u] + t] : 0.0f;
-        const float bv = boff[u] >= 0 ? Qs[boff[u] + p.s * t] : 0.0f;
-        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[u], 0, 0, 0);
-      }
+    for (int i = 0; i < QMAX; ++i) {
+      const int c = qcu[i] >= 0 ? qcu[i] >> 16 : 0;
+      const int q = min(max(q0 + (qcu[i] & 0xffff), 0), p.Lq - 1);
+      qv[i] = Qb[(int64_t)c * p.Lq + q];
     }
+  };
+  // branch-free: a thread's slots past the chunk go to its own sink word, so
+  // that every register of the batch is consumed on every path
+  float* sink = Qs + (p.Cc + 1) * p.qs + tid;
+  for (int e = tid; e < WPS; e += WTH) Ps[p.Ca * WPS + e] = 0.0f;
+  for (int e = tid; e < p.qs; e += WTH) Qs[p.Cc * p.qs + e] = 0.0f;
+  auto stage = [&](int chunk) {
+    const int t0 = (chunk % p.tchunks) * WT, q0 = p.s * t0 - p.pad;
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i) {
+      const int e = tid + WTH * i;
+      float* d = e < np ? Ps + (e / WT) * WPS + e % WT : sink;
+      *d = t0 + e % WT < p.Lp ? pv[i] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < QMAX; ++i) {
+      const int q = q0 + (qcu[i] & 0xffff);
+      float* d = qcu[i] >= 0 ? Qs + (qcu[i] >> 16) * p.qs + (qcu[i] & 0xffff) : sink;
+      *d = (q >= 0 && q < p.Lq) ? qv[i] : 0.0f;
+    }
+  };
+  const int nk = p.Cc * p.k;               // GEMM columns
+  const int MTa = (p.Ca + 15) / 16, NTn = (nk + 15) / 16, ntile = MTa * NTn;
+  // wave groups splitting the K steps: as many as the idle waves allow
+  const int ksp = wgrad_ksp(ntile);
+  const int nwk = WNW / ksp;               // waves per group
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int slice = wave / nwk, wl = wave - slice * nwk;
+  const int lr = lane & 15, lk = lane >> 4;
+  // this lane's LDS offsets for each of its tiles (tile u of the wave is
+  // wl + nwk u): A row a = 16 mt + lr, B column n = 16 nt + lr = (c, j)
+  int aoff[NTMAX], boff[NTMAX];
+#pragma unroll
+  for (int u = 0; u < NTMAX; ++u) {
+    const int tile = wl + nwk * u;
+    const int mt = tile / NTn, nt = tile - mt * NTn;
+    const int a = 16 * mt + lr, nn = 16 * nt + lr;
+    aoff[u] = (tile < ntile && a < p.Ca) ? a * WPS : p.Ca * WPS;
+    boff[u] = (tile < ntile && nn < nk) ? (nn / p.k) * p.qs + (nn % p.k) : p.Cc * p.qs;
+  }
+  wf32x4 acc[NTMAX];
+#pragma unroll
+  for (int u = 0; u < NTMAX; ++u) acc[u] = wf32x4{0.f, 0.f, 0.f, 0.f};
+  // this wave's tiles: wl, wl + nwk, ... below ntile
+  const int mytiles = wl < ntile ? (ntile - wl + nwk - 1) / nwk : 0;
+  const int G = gridDim.x;
+  const int c0 = (int)((int64_t)p.nchunk * blockIdx.x / G), c1 = (int)((int64_t)p.nchunk * (blockIdx.x + 1) / G);
+  if (c0 < c1) fetch(c0);
+  for (int chunk = c0; chunk < c1; ++chunk) {
+    __syncthreads();  // the previous chunk's reads are done
+    stage(chunk);
+    __syncthreads();
+    if (chunk + 1 < c1) fetch(chunk + 1);  // in flight during this chunk's MFMAs
+#define GW_WG_CASE(N)                                                          \
+  case N:                                                                      \
+    if constexpr (N <= NTMAX) wgrad_mma<N, WT>(Ps, Qs, aoff, boff, p.s, slice, ksp, lk, acc); \
+    break;
+    switch (mytiles) {  // wave-uniform
+      GW_WG_CASE(1)
+      GW_WG_CASE(2)
+      GW_WG_CASE(3)
+      GW_WG_CASE(4)
+      GW_WG_CASE(5)
+      GW_WG_CASE(6)
+      GW_WG_CASE(7)
+      default: break;
+    }
+#undef GW_WG_CASE
+  }
+  // groups 1.. hand their accumulators to group 0 through LDS, which adds
+  // them in group order
+  if (ksp > 1) {
+    float* xs = lds;  // [group - 1][wl][u][lane][4]
+    const int tpw = (ntile + nwk - 1) / nwk;
+    __syncthreads();
+    if (slice > 0)
+#pragma unroll
+      for (int u = 0; u < NTMAX; ++u) {
+        if (u >= tpw) break;
+        float* d = xs + ((((slice - 1) * nwk + wl) * tpw + u) * 64 + lane) * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[r] = acc[u][r];
+      }
+    __syncthreads();
+    if (slice == 0)
+      for (int g = 1; g < ksp; ++g)
+#pragma unroll
+        for (int u = 0; u < NTMAX; ++u) {
+          if (u >= tpw) break;
+          const float* d = xs + ((((g - 1) * nwk + wl) * tpw + u) * 64 + lane) * 4;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[u][r] += d[r];
+        }
+    if (slice > 0) return;
   }
   // D[row = 4 lk + r][col = lr] of tile u: weight (a, n)
   const int nw = p.Ca * nk;
   float* out = p.partial + (int64_t)blockIdx.x * nw;
 #pragma unroll
-  for (int u = 0; u < WTPW; ++u) {
-    const int tile = wave + WNW * u;
+  for (int u = 0; u < NTMAX; ++u) {
+    const int tile = wl + nwk * u;
     if (tile >= ntile) break;
     const int mt = tile / NTn, nt = tile - mt * NTn;
     const int nn = 16 * nt + lr;
@@ -318,6 +542,8 @@ __global__ __launch_bounds__(64 * WNW, 2) void wgrad_partial(WgP p) {
   }
 }
 
+// partials q of group g added in order q = 64 g, 64 g + 1, ...; the loads of
+// 16 partials are issued together
 __global__ __launch_bounds__(256) void wgrad_group(const float* partial, int nchunk, int nw,
                                                    double* mid) {
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -325,7 +551,15 @@ __global__ __launch_bounds__(256) void wgrad_group(const float* partial, int nch
   if (e >= nw) return;
   double acc = 0.0;
   const int q1 = min(nchunk, (g + 1) * WG);
-  for (int q = g * WG; q < q1; ++q) acc += (double)partial[(int64_t)q * nw + e];
+  int q = g * WG;
+  for (; q + 16 <= q1; q += 16) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = partial[(int64_t)(q + j) * nw + e];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc += (double)v[j];
+  }
+  for (; q < q1; ++q) acc += (double)partial[(int64_t)q * nw + e];
   mid[(int64_t)g * nw + e] = acc;
 }
 
@@ -334,12 +568,25 @@ __global__ __launch_bounds__(256) void wgrad_final(const double* mid, int ngroup
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nw) return;
   double acc = 0.0;
-  for (int g = 0; g < ngroup; ++g) acc += mid[(int64_t)g * nw + e];
+  int g = 0;
+  for (; g + 8 <= ngroup; g += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = mid[(int64_t)(g + j) * nw + e];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  for (; g < ngroup; ++g) acc += mid[(int64_t)g * nw + e];
   dw[e] = (float)acc;
 }
 
 hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, int Lq, int n,
                         int k, int stride, int pad, void* scratch, float* dw, hipStream_t st) {
+  const int cfg = wgrad_cfg(Ca, Cc, k, stride);
+  const int nw = Ca * Cc * k;
+  // every accumulator tile of the GEMM must have a register slot in its wave
+  if (cfg < 0 || ((Ca + 15) / 16) * ((Cc * k + 15) / 16) > WNW * WTPW) return hipErrorInvalidValue;
+  const int wt = kWgCfg[cfg].wt;
   WgP p;
   p.P = P;
   p.Q = Q;
@@ -351,19 +598,23 @@ hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, 
   p.k = k;
   p.s = stride;
   p.pad = pad;
-  p.tchunks = (Lp + WT - 1) / WT;
-  p.nchunk = wgrad_chunks(n, Lp);
-  const int nw = Ca * Cc * k;
-  const int G = wgrad_blocks(n, Lp, nw);
+  p.tchunks = (Lp + wt - 1) / wt;
+  p.nchunk = wgrad_chunks(n, Lp, wt);
+  p.qs = wgrad_qs(stride * (wt - 1) + k);
+  const int G = wgrad_blocks(p.nchunk);
   const int ngroup = (G + WG - 1) / WG;
   p.partial = reinterpret_cast<float*>(scratch);
   double* mid = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) +
                                           ((((size_t)G * nw * sizeof(float)) + 255) & ~(size_t)255));
-  const int span = stride * (WT - 1) + k;
-  const size_t lds = sizeof(float) * ((size_t)Ca * WPS + (size_t)Cc * span);
-  // every accumulator tile of the GEMM must have a register slot in its wave
-  if (lds > 64 * 1024 || ((Ca + 15) / 16) * ((Cc * k + 15) / 16) > WNW * WTPW) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(wgrad_partial, dim3(G), dim3(64 * WNW), lds, st, p);
+  const size_t lds = wgrad_lds(Ca, Cc, k, stride, wt);
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((wgrad_partial<1024, 8, 24, 3>), dim3(G), dim3(WTH), lds, st, p); break;
+    case 1: hipLaunchKernelGGL((wgrad_partial<512, 8, 24, 3>), dim3(G), dim3(WTH), lds, st, p); break;
+    case 2: hipLaunchKernelGGL((wgrad_partial<256, 8, 24, 3>), dim3(G), dim3(WTH), lds, st, p); break;
+    case 3: hipLaunchKernelGGL((wgrad_partial<128, 8, 12, 3>), dim3(G), dim3(WTH), lds, st, p); break;
+    case 4: hipLaunchKernelGGL((wgrad_partial<64, 8, 12, 7>), dim3(G), dim3(WTH), lds, st, p); break;
+    default: hipLaunchKernelGGL((wgrad_partial<64, 16, 24, 7>), dim3(G), dim3(WTH), lds, st, p); break;
+  }
   hipLaunchKernelGGL(wgrad_group, dim3((nw + 255) / 256, ngroup), dim3(256), 0, st, p.partial,
                      G, nw, mid);
   hipLaunchKernelGGL(wgrad_final, dim3((nw + 255) / 256), dim3(256), 0, st, mid, ngroup, nw, dw);
