@@ -34,6 +34,7 @@ window, the retraining step, and PCIe-inclusive serving through serve.py.
 from __future__ import annotations
 
 import argparse
+import collections
 import gc
 import json
 import os
@@ -341,10 +342,23 @@ def d0_latency(dev, reps=50):
             "config": "DeepClean FP32, 21 x 4096 (1 s at 4096 Hz), batch 1"}
 
 
-def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
-    """Serving loop (continuous batching, host requests staged through pinned
-    memory, so PCIe-inclusive) on the same 256-stream mix: a closed-loop run
-    and open-loop Poisson arrivals at the given aggregate update rates."""
+def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn, phases=(1, 2, 4, 8)):
+    """Serving loop (continuous batching; clients receive their new samples
+    straight into pinned staging memory handed out by the server, so the
+    copy to the device is PCIe-inclusive) on the same 256-stream mix.
+
+    Closed loop: every stream keeps one update outstanding and sends the next
+    as soon as its previous result is back.  The loop is event driven: it
+    receives the next updates of the streams whose results came back,
+    launches a step after every N/P receives (N streams, P the batch
+    divisor), and polls for completed steps every 16 receives, so results
+    are taken as they finish and one batch's host work overlaps the others'
+    device work.  The clients' receives (the copies of their new samples into
+    the handed-out buffers) run on the serving thread (per-request copies of
+    tens of KB keep the interpreter lock, so receiver threads would only
+    contend for it).  Larger P: smaller, more frequent steps, lower latency.  Open loop: Poisson arrivals at the given aggregate
+    update rates.  Latency runs from a request's arrival (its samples
+    complete in memory) to its result on the host."""
     import torch
 
     from paper_2108_12430_amd.serve import HipExecutor, Server
@@ -358,8 +372,7 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
     arena = N_DC * ring(DC_C, DC_W) + N_BB * ring(BB_C, BB_W) + (64 << 20)
     out = {}
 
-    # each stream's requests: contiguous float32 host arrays prepared before
-    # the timed loops (as a client's receive buffers would be), 8 per stream
+    # each stream's source blocks (what its receive delivers), 8 per stream
     # used in turn
     NPRE = 8
     pre = []
@@ -371,19 +384,33 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
                            np.ascontiguousarray(src_s[o:o + s]) if model == "dc" else None))
         pre.append(blocks)
 
-    def sample(i, k):
-        return pre[i][k % NPRE]
+    def fill(r, i, k):
+        x, st = pre[i][k % NPRE]
+        np.copyto(r.samples, x)
+        if st is not None:
+            np.copyto(r.strain, st)
 
-    def run(arrivals, closed):
+    def receive(srv, sid, i, k, t_arrival=None):
+        """Client i's k-th update, received into a handed-out buffer."""
+        r = srv.reserve(sid, specs[i][3])
+        fill(r, i, k)
+        return srv.commit(r, t_arrival)
+
+    def receive_batch(srv, batch):
+        for sid, i, k in batch:
+            receive(srv, sid, i, k)
+
+    def run(arrivals, nphase=2):
         ex = HipExecutor({"dc": dc, "bbh": bb}, arena_bytes=arena, max_slots=len(specs),
                          max_items=len(specs), precision=prec)
-        srv = Server(ex, max_inflight=4)
+        srv = Server(ex, max_inflight=nphase + 1)
         sids = [srv.open_stream(m, C, W) for (m, C, W, s) in specs]
-        # warm-up: one request per stream
-        for i, sid in enumerate(sids):
-            x, st = sample(i, 0)
-            srv.submit(sid, x, st)
-        srv.drain()
+        index = {sid: i for i, sid in enumerate(sids)}
+        # warm-up: a few requests per stream (staging pages, workspaces)
+        for k in range(3):
+            for i, sid in enumerate(sids):
+                receive(srv, sid, i, k)
+            srv.drain()
         srv.completed.clear()
         torch.cuda.synchronize()
         # requests form no reference cycles; the cyclic collector's full passes
@@ -393,26 +420,50 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
         gc.disable()
         t0 = time.perf_counter()
         nsamp = 0
-        if closed:
-            k = 1
-            while time.perf_counter() - t0 < seconds:
-                for i, sid in enumerate(sids):
-                    x, st = sample(i, k)
-                    srv.submit(sid, x, st)
+        if arrivals is None:
+            cnt = [3] * len(specs)
+            todo = collections.deque(range(len(specs)))  # streams whose next update is due
+            per_step = (len(specs) + nphase - 1) // nphase
+            seen = 0
+            stop = False
+
+            def retire():
+                nonlocal seen, nsamp
+                srv.poll()
+                done = srv.completed
+                for r in done[seen:]:
+                    i = index[r.stream]
                     nsamp += specs[i][3]
-                srv.step()
-                k += 1
-            srv.drain()
+                    todo.append(i)
+                seen = len(done)
+
+            while True:
+                n = 0
+                while todo and n < per_step and not stop:
+                    i = todo.popleft()
+                    receive(srv, sids[i], i, cnt[i])
+                    cnt[i] += 1
+                    n += 1
+                    if n % 16 == 0:
+                        retire()
+                if srv.pending():
+                    srv.step()
+                retire()
+                stop = stop or time.perf_counter() - t0 >= seconds
+                if not todo or stop:
+                    if not srv.inflight and not srv.pending():
+                        break
+                    srv.wait()
+                    retire()
         else:
             idx = 0
-            cnt = [1] * len(specs)
+            cnt = [3] * len(specs)
             while idx < len(arrivals) or srv.pending() or srv.inflight:
                 now = time.perf_counter() - t0
                 while idx < len(arrivals) and arrivals[idx][0] <= now:
                     ta, i = arrivals[idx]
-                    x, st = sample(i, cnt[i])
+                    receive(srv, sids[i], i, cnt[i], t_arrival=t0 + ta)
                     cnt[i] += 1
-                    srv.submit(sids[i], x, st, t_arrival=t0 + ta)
                     nsamp += specs[i][3]
                     idx += 1
                 if srv.pending():
@@ -427,8 +478,12 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
         st_["steps"] = srv.steps
         return st_
 
-    out["closed_loop"] = run(None, True)
-    log_fn(f"bench: serving closed loop {out['closed_loop']}")
+    out["closed_loop"] = []
+    for P in phases:
+        res = run(None, P)
+        res["phases"] = P
+        out["closed_loop"].append(res)
+        log_fn(f"bench: serving closed loop, {P} phase groups: {res}")
     strides = np.array([s for *_, s in specs], np.float64)
     w = 1.0 / strides
     out["open_loop"] = []
@@ -442,7 +497,7 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn):
                 arr.append((t, i))
                 t += rng.exponential(1.0 / r)
         arr.sort()
-        res = run(arr, False)
+        res = run(arr)
         res["rate"] = lam
         out["open_loop"].append(res)
         log_fn(f"bench: serving open loop {lam}/s: {res}")
@@ -478,6 +533,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--train-only", action="store_true",
                     help="time only the training step (FP32 and BF16-conv; --steps/--warmup apply), for profiling")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving-loop leg (closed and open loop), for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -485,7 +542,7 @@ def main():
         sys.exit(2)
 
     cpu = None
-    if not args.no_cpu and not args.train_only:
+    if not args.no_cpu and not args.train_only and not args.serve_only:
         # before anything touches the GPU: the oracle workers are new processes
         dc_s0, bb_s0 = make_mix()
         cpu = cpu_baseline(dc_s0, bb_s0)
@@ -523,6 +580,10 @@ def main():
             raise
         log(f"bench: {args.precision} path unavailable ({e}); measuring fp32")
         args.precision, prec = "fp32", gs.FP32
+    if args.serve_only:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        print(json.dumps({"serving": serve_bench(dc, bb, prec, dc_s, bb_s, rates, args.serve_seconds, log)}))
+        return
 
     # pool with every stream admitted
     ring = lambda c, w: ((c * w * 4 + 255) // 256 + (c * w * 2 + 255) // 256) * 256

@@ -41,6 +41,7 @@ class Request:
     seq: int = 0
     t_done: Optional[float] = None
     result: Any = None             # clean strain [s] (DeepClean) or logit (BBHnet)
+    stage: Any = None              # executor staging token of a reserved request
 
     @property
     def latency(self) -> Optional[float]:
@@ -150,8 +151,49 @@ class Server:
             self._ready[sid] = None
         return r
 
+    def reserve(self, sid: int, s: int) -> Request:
+        """Hand the client a request whose ``samples`` ([C][s]) and, for
+        DeepClean streams, ``strain`` ([s]) are views into the executor's
+        pinned staging memory: the client writes its new samples there (its
+        receive) and then calls ``commit``.  Requests committed in the order
+        they were reserved reach the device without a host-side copy."""
+        st = self.streams[sid]
+        if st.closing:
+            raise ValueError("stream is closing")
+        if not (1 <= s <= st.W):
+            raise ValueError(f"stream {sid} takes 1..{st.W} new samples, got {s}")
+        x, strain, tok = self.ex.reserve(st.model, st.C, st.W, int(s))
+        return Request(sid, x, strain, 0.0, stage=tok)
+
+    def commit(self, r: Request, t_arrival: Optional[float] = None) -> Request:
+        """Queue a reserved request whose buffers the client has filled; its
+        arrival time is now (the moment its data is complete) unless given."""
+        st = self.streams.get(r.stream)
+        if st is None or st.closing:
+            self.cancel(r)
+            raise ValueError("stream is closed or closing")
+        r.t_arrival = self.clock() if t_arrival is None else t_arrival
+        r.seq = st.next_seq
+        st.next_seq += 1
+        st.pending.append(r)
+        self._npending += 1
+        if r.stream not in self._ready:
+            self._ready[r.stream] = None
+        return r
+
+    def cancel(self, r: Request) -> None:
+        """Give back a reserved request's staging memory without queueing it."""
+        if r.stage is not None:
+            self.ex.release(r.stage)
+            r.stage = None
+
     def pending(self) -> int:
         return self._npending
+
+    def wait(self) -> None:
+        """Block until the oldest in-flight group completes, and retire it."""
+        if self.inflight:
+            self._complete_oldest(block=True)
 
     # ---- the loop ----------------------------------------------------------
     def step(self) -> int:
@@ -217,16 +259,44 @@ class Server:
 # Device executor
 # ---------------------------------------------------------------------------
 
+class _Page:
+    """One pinned staging page of a group: samples and strain regions, filled
+    by bump allocation in reservation order."""
+
+    __slots__ = ("x", "s", "xn", "sn", "cx", "cs", "nx", "ns", "refs", "ev", "seq")
+
+    def __init__(self, torch, nx, ns):
+        self.x = torch.empty(nx, dtype=torch.float32, pin_memory=True)
+        self.s = torch.empty(max(ns, 1), dtype=torch.float32, pin_memory=True)
+        self.xn = self.x.numpy()
+        self.sn = self.s.numpy()
+        self.cx, self.cs = nx, max(ns, 1)  # capacities
+        self.nx = self.ns = 0
+        self.refs = 0     # reserved requests not yet launched
+        self.ev = None    # event after the last launch that copied from the page
+        self.seq = 0      # fill order (pages are used round-robin)
+
+
 class HipExecutor:
-    """Runs each group on the device through the C ABI: one pinned host
-    staging copy of the group's new samples (and strain), one batched
-    snapshot_update, one batched forward (DeepClean: fully-online clean
-    strain; BBHnet: logits) and one copy of the results back, all on the
-    group's own HIP stream, completed by an event.  Staging and output
-    buffers are preallocated per group in a small ring and reused once the
-    work that used them has completed."""
+    """Runs each group on the device through the C ABI: the group's new
+    samples (and strain) reach the device by one host-to-device copy per
+    staging run, then one batched snapshot_update, one batched forward
+    (DeepClean: fully-online clean strain; BBHnet: logits) and one copy of
+    the results back, all on the group's own HIP stream, completed by an
+    event.
+
+    Reserved requests (Server.reserve) live in the group's pinned staging
+    pages; a launch whose requests form contiguous runs of those pages copies
+    the runs directly (no host-side copy; the requests are processed in page
+    order and their results returned in the caller's order).  Other launches
+    (requests submitted as client arrays, or a reservation order that leaves
+    gaps) are packed into a per-group pinned staging ring first.  Device
+    buffers and the packing ring are preallocated per group and reused once
+    the work that used them has completed."""
 
     RING = 6  # per-group buffer sets; must exceed the server's max_inflight
+    PAGE = 1 << 22  # floats of samples per staging page (16 MiB)
+    MAX_PAGES = 6   # pages per group before a full page is waited on
 
     def __init__(self, models: Dict[str, Any], arena_bytes: int, max_slots: int = 1024, max_items: int = 1024,
                  precision: int = 1, device: str = "cuda:0"):
@@ -244,6 +314,10 @@ class HipExecutor:
         self.ws_n: Dict[Tuple[str, int, int], int] = {}
         self.bufs: Dict[Tuple[str, int, int], List[Dict[str, Any]]] = {}
         self.next_buf: Dict[Tuple[str, int, int], int] = {}
+        self.pages: Dict[Tuple[str, int, int], List[_Page]] = {}
+        self.cur: Dict[Tuple[str, int, int], _Page] = {}
+        self._page_seq = 0
+        self._is_dc: Dict[str, bool] = {}
 
     def _stream(self, key):
         st = self.streams.get(key)
@@ -258,6 +332,85 @@ class HipExecutor:
 
     def close(self, slot):
         self.pool.close(slot)
+
+    # ---- pinned staging pages ---------------------------------------------
+    def _new_page(self, key, nx, ns):
+        """A page with room for nx samples and ns strain values: a drained
+        page of the group (no reservations left, last copy complete), else a
+        new one, else (MAX_PAGES reached) the oldest drained page once its
+        copy has completed."""
+        pages = self.pages.setdefault(key, [])
+        is_dc = isinstance(self.models[key[0]], self.gs.DeepClean)
+        want_x = max(nx, self.PAGE)
+        want_s = max(ns, self.PAGE // key[1] if is_dc else 0)
+        pick = None
+        for pg in sorted(pages, key=lambda q: q.seq):
+            if pg is self.cur.get(key) or pg.refs or pg.cx < nx or pg.cs < ns:
+                continue
+            if pg.ev is None or pg.ev.query():
+                pick = pg
+                break
+        if pick is None and len(pages) < self.MAX_PAGES:
+            pick = _Page(self.torch, want_x, want_s)
+            pages.append(pick)
+        if pick is None:
+            for pg in sorted(pages, key=lambda q: q.seq):
+                if pg is not self.cur.get(key) and not pg.refs and pg.cx >= nx and pg.cs >= ns:
+                    pick = pg
+                    break
+            if pick is None:  # every page holds reservations: grow
+                pick = _Page(self.torch, want_x, want_s)
+                pages.append(pick)
+            elif pick.ev is not None:
+                pick.ev.synchronize()
+        pick.nx = pick.ns = 0
+        pick.ev = None
+        self._page_seq += 1
+        pick.seq = self._page_seq
+        self.cur[key] = pick
+        return pick
+
+    def reserve(self, model, C, W, s):
+        key = (model, C, W)
+        is_dc = self._is_dc.get(model)
+        if is_dc is None:
+            is_dc = self._is_dc[model] = isinstance(self.models[model], self.gs.DeepClean)
+        nx, ns = C * s, (s if is_dc else 0)
+        pg = self.cur.get(key)
+        if pg is None or pg.nx + nx > pg.cx or pg.ns + ns > pg.cs:
+            pg = self._new_page(key, nx, ns)
+        ox, os_ = pg.nx, pg.ns
+        pg.nx += nx
+        pg.ns += ns
+        pg.refs += 1
+        x = pg.xn[ox:ox + nx].reshape(C, s)
+        strain = pg.sn[os_:os_ + ns] if is_dc else None
+        return x, strain, (pg, ox, os_)
+
+    def release(self, tok):
+        tok[0].refs -= 1
+
+    def _runs(self, items, C, is_dc):
+        """The launch order (page fill order) and the contiguous staging runs
+        [(page, x0, nx, s0, ns)] of a group's items, or None when any item is
+        not staged or the pages leave gaps between them."""
+        toks = [r.stage for _, r in items]
+        if any(t is None for t in toks):
+            return None
+        order = sorted(range(len(items)), key=lambda k: (toks[k][0].seq, toks[k][1]))
+        runs = []
+        for k in order:
+            pg, ox, os_ = toks[k]
+            s = items[k][1].samples.shape[1]
+            nx, ns = C * s, (s if is_dc else 0)
+            if runs and runs[-1][0] is pg and runs[-1][1] + runs[-1][2] == ox and runs[-1][3] + runs[-1][4] == os_:
+                r = runs[-1]
+                runs[-1] = (pg, r[1], r[2] + nx, r[3], r[4] + ns)
+            elif runs and runs[-1][0] is pg:
+                return None  # a gap inside a page (a request staged but not in this launch)
+            else:
+                runs.append((pg, ox, nx, os_, ns))
+        return order, runs
 
     def _ws(self, key, n):
         """Workspace of a group, allocated on (and only used on) its stream."""
@@ -308,28 +461,43 @@ class HipExecutor:
         st = self._stream(key)
         m = self.models[model]
         is_dc = isinstance(m, self.gs.DeepClean)
-        slots = [s for s, _ in items]
-        strides = np.fromiter((r.samples.shape[1] for _, r in items), dtype=np.int64, count=len(items))
+        staged = self._runs(items, C, is_dc)
+        order = staged[0] if staged is not None else list(range(len(items)))
+        its = [items[k] for k in order]
+        slots = [s for s, _ in its]
+        strides = np.fromiter((r.samples.shape[1] for _, r in its), dtype=np.int64, count=len(its))
         sizes = C * strides
-        offsets = np.zeros(len(items), np.int64)
+        offsets = np.zeros(len(its), np.int64)
         np.cumsum(sizes[:-1], out=offsets[1:])
         n_f = int(sizes.sum())
         s_tot = int(strides.sum())
-        n_out = s_tot if is_dc else len(items)
+        n_out = s_tot if is_dc else len(its)
         b = self._buf(key, n_f, s_tot if is_dc else 0, n_out)
-        np.concatenate([r.samples.reshape(-1) for _, r in items], out=b["h_x"].numpy()[:n_f])
-        if is_dc:
-            np.concatenate([r.strain if r.strain is not None else np.zeros(r.samples.shape[1], np.float32)
-                            for _, r in items], out=b["h_s"].numpy()[:s_tot])
-        ws = self._ws(key, len(items))
+        if staged is None:
+            np.concatenate([r.samples.reshape(-1) for _, r in its], out=b["h_x"].numpy()[:n_f])
+            if is_dc:
+                np.concatenate([r.strain if r.strain is not None else np.zeros(r.samples.shape[1], np.float32)
+                                for _, r in its], out=b["h_s"].numpy()[:s_tot])
+        ws = self._ws(key, len(its))
         with torch.cuda.stream(st):
             dx = b["d_x"][:n_f]
-            dx.copy_(b["h_x"][:n_f], non_blocking=True)
+            ds = b["d_s"][:s_tot] if is_dc else None
+            if staged is None:
+                dx.copy_(b["h_x"][:n_f], non_blocking=True)
+                if is_dc:
+                    ds.copy_(b["h_s"][:s_tot], non_blocking=True)
+            else:
+                # the runs are consecutive in launch order: packed on the device
+                px = ps = 0
+                for pg, x0, nx, s0, ns in staged[1]:
+                    dx[px:px + nx].copy_(pg.x[x0:x0 + nx], non_blocking=True)
+                    if ns:
+                        ds[ps:ps + ns].copy_(pg.s[s0:s0 + ns], non_blocking=True)
+                    px += nx
+                    ps += ns
             self.pool.update(slots, strides, dx, offsets, stream=st)
             out = b["d_o"][:n_out]
             if is_dc:
-                ds = b["d_s"][:s_tot]
-                ds.copy_(b["h_s"][:s_tot], non_blocking=True)
                 m.forward(pool=self.pool, slots=slots, W=W, strides=strides, strain=ds, clean=out,
                           precision=self.precision, ws=ws, stream=st)
             else:
@@ -339,7 +507,17 @@ class HipExecutor:
             ev = torch.cuda.Event()
             ev.record(st)
         b["ev"] = ev
-        return {"ev": ev, "buf": b, "n_out": n_out, "strides": strides, "dc": is_dc}
+        # staging pages: the launch's reservations are consumed; a page is
+        # reused only after this launch's copies from it have completed
+        for _, r in its:
+            if r.stage is not None:
+                pg = r.stage[0]
+                pg.refs -= 1
+                if staged is not None:
+                    pg.ev = ev
+                r.stage = None
+        return {"ev": ev, "buf": b, "n_out": n_out, "strides": strides, "dc": is_dc,
+                "order": order if staged is not None else None}
 
     def poll(self, h):
         return h["ev"].query()
@@ -348,9 +526,16 @@ class HipExecutor:
         h["ev"].synchronize()
         out = h["buf"]["h_o"].numpy()[:h["n_out"]].copy()
         if not h["dc"]:
-            return list(out)
-        res, o = [], 0
-        for s in h["strides"]:
-            res.append(out[o:o + s])
-            o += s
-        return res
+            res = list(out)
+        else:
+            res, o = [], 0
+            for s in h["strides"]:
+                res.append(out[o:o + s])
+                o += s
+        order = h["order"]
+        if order is None:
+            return res
+        back = [None] * len(res)
+        for k, v in zip(order, res):
+            back[k] = v
+        return back

@@ -41,8 +41,10 @@ def make_requests():
     return out
 
 
-def serve(models, spec_idx, data, interleave_seed=None, arena=64 << 20):
+def serve(models, spec_idx, data, interleave_seed=None, arena=64 << 20, handout=False, page=None):
     ex = HipExecutor(models, arena_bytes=arena, precision=gs.BF16)
+    if page is not None:
+        ex.PAGE = page
     srv = Server(ex)
     sids = {i: srv.open_stream(SPECS[i][0], SPECS[i][1], SPECS[i][2]) for i in spec_idx}
     reqs = {i: [] for i in spec_idx}
@@ -57,7 +59,16 @@ def serve(models, spec_idx, data, interleave_seed=None, arena=64 << 20):
     for n, (i, k) in enumerate(order):
         model, C, W, s = SPECS[i]
         wit, strain = data[i]
-        r = srv.submit(sids[i], wit[:, k * s:(k + 1) * s], None if strain is None else strain[k * s:(k + 1) * s])
+        if handout:
+            # the client receives straight into the pinned staging memory
+            r = srv.reserve(sids[i], s)
+            r.samples[...] = wit[:, k * s:(k + 1) * s]
+            if strain is not None:
+                r.strain[...] = strain[k * s:(k + 1) * s]
+            srv.commit(r)
+        else:
+            r = srv.submit(sids[i], wit[:, k * s:(k + 1) * s],
+                           None if strain is None else strain[k * s:(k + 1) * s])
         reqs[i].append(r)
         if rng.uniform() < 0.3:
             srv.step()                       # steps interleave with arrivals
@@ -77,6 +88,27 @@ def test_mix_equals_alone_bitwise(models):
         alone, _ = serve(mdl, [i], data)
         for a, b in zip(alone[i], mixed[i]):
             assert np.array_equal(np.asarray(a.result), np.asarray(b.result)), (SPECS[i], a.seq)
+
+
+@pytest.mark.parametrize("page", [1 << 22, 40000])
+def test_handout_equals_submit_bitwise(models, page):
+    """Requests received into the executor's pinned staging pages (reserve /
+    commit) give bitwise the results of client arrays (submit).  The
+    interleaved arrivals leave some streams two requests deep, so launches
+    mix direct page runs with the packing fallback; the small page size makes
+    launches span several pages and pages get reused."""
+    mdl, _, _ = models
+    data = make_requests()
+    idx = list(range(len(SPECS)))
+    a, _ = serve(mdl, idx, data, interleave_seed=11)
+    b, srv = serve(mdl, idx, data, interleave_seed=11, handout=True, page=page)
+    for i in idx:
+        for x, y in zip(a[i], b[i]):
+            assert np.array_equal(np.asarray(x.result), np.asarray(y.result)), (SPECS[i], x.seq)
+    pages = srv.ex.pages
+    assert all(pg.refs == 0 for v in pages.values() for pg in v)
+    if page < 1 << 20:
+        assert any(len(v) > 1 for v in pages.values())
 
 
 def test_serving_results_match_oracle(models):
