@@ -229,14 +229,13 @@ def traffic_for(kernel):
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_serving_mix_bf16.json")
     try:
-        d = json.load(open(path))
-        src = open(os.path.join(ROOT, d["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        k = json.load(open(path))["kernels"][kernel]
+        src = open(os.path.join(ROOT, k["source"]), "rb").read()
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+    if hashlib.sha256(src).hexdigest() != k.get("source_sha256"):
         return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_launch"])
+    return float(k["bytes_per_launch"])
 
 
 def train_bench(dev, steps=5, warmup=2, B=32, W=DC_W, recompute=True, precision="fp32"):

@@ -4,6 +4,8 @@
         --title TITLE --cmd-trace CMD --cmd-fetch CMD --cmd-write CMD
     python -m paper_2108_12430_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON
     python -m paper_2108_12430_amd.profsum util COUNTER_CSV OUT_MD --title TITLE --cmd CMD
+    python -m paper_2108_12430_amd.profsum stats STATS_CSV OUT_MD --title TITLE --cmd CMD \
+        [--trace TRACE_CSV --marker NAME]
 
 STATS_CSV is the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats`` run;
 FETCH_CSV / WRITE_CSV are the ``*_counter_collection.csv`` files of two
@@ -23,13 +25,16 @@ import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
-# bench launch name -> rocprof kernel name, for the kernels whose traffic
-# bench.py reports
+# bench launch name -> (rocprof kernel name, source file), for the kernels
+# whose traffic bench.py reports; each entry is valid while its source's
+# hash is unchanged
 KERNELS = {
-    "dc_fused_bf16": "void gw::dc_fused<2, false>(gw::ConvP, gw::FusedP, int)",
-    "snapshot": "gw::snapshot_kernel(char*, gw::Item const*, float const*)",
+    "dc_fused_bf16": ("void gw::dc_fused<2, false>(gw::ConvP, gw::FusedP, int)",
+                      "paper_2108_12430_amd/csrc/conv_bf16.hip"),
+    "bbh_fused": ("gw::bbh_fused(gw::BbFusedP)", "paper_2108_12430_amd/csrc/bbh_fused.hip"),
+    "snapshot": ("gw::snapshot_kernel(char*, gw::Item const*, float const*)",
+                 "paper_2108_12430_amd/csrc/misc.hip"),
 }
-SOURCE = "paper_2108_12430_amd/csrc/conv_bf16.hip"
 
 
 def _per_kernel(path):
@@ -79,18 +84,18 @@ def traffic(a):
     F, Wr = _per_kernel(a.fetch), _per_kernel(a.write)
     ff, _ = _factor(F)
     fw, _ = _factor(Wr)
-    src = open(os.path.join(ROOT, SOURCE), "rb").read()
     res = {"_about": "HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE passes, scaled by a 1 GiB "
-                     "device copy; valid only while the kernel source hash matches",
-           "fetch_factor": ff, "write_factor": fw, "source": SOURCE,
-           "source_sha256": hashlib.sha256(src).hexdigest(), "kernels": {}}
-    for name, rk in KERNELS.items():
+                     "device copy; an entry is valid only while its kernel source hash matches",
+           "fetch_factor": ff, "write_factor": fw, "kernels": {}}
+    for name, (rk, source) in KERNELS.items():
         if rk not in F or rk not in Wr:
             continue
         f = sum(F[rk]) / len(F[rk])
         w = sum(Wr[rk]) / len(Wr[rk])
-        res["kernels"][name] = {"rocprof_name": rk, "fetch_kib": f, "write_kib": w,
-                                "bytes_per_launch": (f * ff + w * fw) * 1024}
+        src = open(os.path.join(ROOT, source), "rb").read()
+        res["kernels"][name] = {"rocprof_name": rk, "source": source,
+                                "source_sha256": hashlib.sha256(src).hexdigest(), "fetch_kib": f,
+                                "write_kib": w, "bytes_per_launch": (f * ff + w * fw) * 1024}
     json.dump(res, open(a.out, "w"), indent=1)
     print(json.dumps(res, indent=1))
 
@@ -135,6 +140,36 @@ def util(a):
     print("\n".join(md))
 
 
+def stats(a):
+    """Kernel-trace summary; with --trace, also the per-kernel time of the
+    last complete step between two dispatches of the marker kernel."""
+    rows = list(csv.DictReader(open(a.stats)))
+    md = [f"# {a.title}", "", "```", a.cmd, "```", "",
+          "PyTorch kernels (`at::native::*`, input set-up) are left out; `total %` is of the whole trace.", "",
+          "| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
+    for r in [r for r in rows if "at::native" not in r["Name"]][:a.top]:
+        md.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if a.trace:
+        tr = sorted(csv.DictReader(open(a.trace)), key=lambda r: int(r["Start_Timestamp"]))
+        idx = [i for i, r in enumerate(tr) if a.marker in r["Kernel_Name"]]
+        if len(idx) >= 2:
+            seg = tr[idx[-2]:idx[-1]]
+            agg = collections.defaultdict(lambda: [0, 0])
+            for r in seg:
+                agg[r["Kernel_Name"]][0] += 1
+                agg[r["Kernel_Name"]][1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            wall = (int(tr[idx[-1]]["Start_Timestamp"]) - int(tr[idx[-2]]["Start_Timestamp"])) / 1e3
+            busy = sum(v[1] for v in agg.values()) / 1e3
+            md += ["", f"Last complete step (from one `{a.marker}` dispatch to the next): {wall:.1f} us wall, "
+                       f"{busy:.1f} us of kernel time, {len(seg)} dispatches.", "",
+                   "| kernel | dispatches | us in the step |", "|---|---|---|"]
+            for k, v in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+                md.append(f"| `{k[:110]}` | {v[0]} | {v[1] / 1e3:.1f} |")
+    open(a.out, "w").write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="sub", required=True)
@@ -153,8 +188,16 @@ def main():
     u.add_argument("out")
     u.add_argument("--title", required=True)
     u.add_argument("--cmd", required=True)
+    k = sub.add_parser("stats")
+    k.add_argument("stats")
+    k.add_argument("out")
+    k.add_argument("--title", required=True)
+    k.add_argument("--cmd", required=True)
+    k.add_argument("--trace")
+    k.add_argument("--marker", default="")
+    k.add_argument("--top", type=int, default=30)
     a = ap.parse_args()
-    {"summary": summary, "traffic": traffic, "util": util}[a.sub](a)
+    {"summary": summary, "traffic": traffic, "util": util, "stats": stats}[a.sub](a)
 
 
 if __name__ == "__main__":
