@@ -78,6 +78,14 @@ __device__ __forceinline__ uint16_t rne(float f) {
   return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? ((u >> 16) | 0x40u) : r);
 }
 
+// two floats -> packed BF16 pair by the hardware conversion (round to nearest
+// even, the same bits as rne)
+__device__ __forceinline__ uint32_t rne2(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
+}
+
 // One convolution of the tile: output tensor TO from input tensor TI (taps
 // KT, input rows SCI r + jj), optionally with the stage's 1x1 shortcut from
 // tensor TS (rows 2 r + 9) added to the same accumulators.  Work unit =
@@ -176,8 +184,8 @@ __device__ __forceinline__ float conv_phase(const uint16_t* in, const uint16_t* 
 #pragma unroll
         for (int e = 0; e < 4; ++e) gsum = fmaf(kh[e], v[e], gsum);
       } else {
-        const uint32_t lo = (uint32_t)rne(v[0]) | ((uint32_t)rne(v[1]) << 16);
-        const uint32_t hi = (uint32_t)rne(v[2]) | ((uint32_t)rne(v[3]) << 16);
+        const uint32_t lo = rne2(v[0], v[1]);
+        const uint32_t hi = rne2(v[2], v[3]);
         *reinterpret_cast<uint2*>(out + prow(TO, r) * RS[TO] + 16 * mt + 4 * lg) = make_uint2(lo, hi);
       }
     }
@@ -187,7 +195,8 @@ __device__ __forceinline__ float conv_phase(const uint16_t* in, const uint16_t* 
 
 }  // namespace bbf
 
-__global__ __launch_bounds__(bbf::NTHR, 2) void bbh_fused(BbFusedP p) {
+// two 8-wave blocks per CU (LDS 76 KB each): four waves per SIMD, at most 128 VGPRs
+__global__ __launch_bounds__(bbf::NTHR, 4) void bbh_fused(BbFusedP p) {
   using namespace bbf;
   __shared__ __attribute__((aligned(16))) uint16_t r0[R0];
   __shared__ __attribute__((aligned(16))) uint16_t r1[R1];
