@@ -1246,6 +1246,7 @@ int cache_layout(const gw_model* m, int W, gw::CacheLayerP& P, size_t* total) {
     off += r256((size_t)g.co * g.Lout * (g.f32 ? 4 : 2));
   }
   P.W = W;
+  P.L = L;
   *total = off;
   return GW_OK;
 }
@@ -1330,15 +1331,6 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     }
   }
   const int L = (int)m->layers.size();
-  // most chunks of dirty positions of each layer over the items (the launch grid)
-  std::vector<int> maxd(L, 0);
-  constexpr int CK = gw::kCacheChunk;
-  for (int i = 0; i < n; ++i)
-    for (int l = 0; l < L; ++l) {
-      int zl, zr;
-      gw::cache_band(P.geo, l, items[i].shift, W, &zl, &zr);
-      maxd[l] = std::max(maxd[l], (zl + CK - 1) / CK + (P.geo[l].Lout - zr + CK - 1) / CK);
-    }
   const void* dev = nullptr;
   StageGuard guard;
   CHK(pool->stager.stage_raw(items.data(), items.size() * sizeof(gw::CacheItem), st, &dev, &guard));
@@ -1349,17 +1341,11 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
   const auto* dit = reinterpret_cast<const gw::CacheItem*>(dev);
   for (int l = 0; l < L; ++l) {
     const LayerD& ly = m->layers[l];
-    P.layer = l;
-    P.wpk = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf);
-    P.scale = reinterpret_cast<const float*>(m->packed + ly.scale);
-    P.shift = reinterpret_cast<const float*>(m->packed + ly.shift);
-    LAUNCH(nm("cache_layer", "L", l), st, gw::launch_cache_layer(dit, n, pool->arena, P, maxd[l], st));
+    P.wpk[l] = reinterpret_cast<const uint16_t*>(m->packed + ly.wbf);
+    P.scale[l] = reinterpret_cast<const float*>(m->packed + ly.scale);
+    P.shift[l] = reinterpret_cast<const float*>(m->packed + ly.shift);
   }
-  if (noise || clean) {
-    int max_s = 0;
-    for (int i = 0; i < n; ++i) max_s = std::max(max_s, (int)items[i].s);
-    LAUNCH("cache_emit", st, gw::launch_cache_emit(dit, n, W, max_s, P.off[L - 1], strain, noise, clean, st));
-  }
+  LAUNCH("cache_forward", st, gw::launch_cache_forward(dit, n, pool->arena, P, strain, noise, clean, st));
   // every cache now holds the current window
   for (int i = 0; i < n; ++i) {
     auto& sl = pool->slots[slots[i]];

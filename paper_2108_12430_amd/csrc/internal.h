@@ -85,11 +85,11 @@ struct CacheGeo {
 constexpr int kCacheMaxLayers = 16;
 struct CacheLayerP {
   CacheGeo geo[kCacheMaxLayers];
-  size_t off[kCacheMaxLayers];  // byte offset of layer l's ring in a stream's cache
-  int layer, W;
-  const uint16_t* wpk;          // the layer's BF16 weight fragments (the per-layer MFMA kernels' packing)
-  const float* scale;           // folded normalisation: y = acc * scale + shift
-  const float* shift;
+  size_t off[kCacheMaxLayers];                // byte offset of layer l's ring in a stream's cache
+  const uint16_t* wpk[kCacheMaxLayers];       // BF16 weight fragments (the per-layer MFMA kernels' packing)
+  const float* scale[kCacheMaxLayers];        // folded normalisation: y = acc * scale + shift
+  const float* shift[kCacheMaxLayers];
+  int L, W;
 };
 // Per-item descriptor of a cached call (staged with the pool's item tables).
 struct CacheItem {
@@ -148,24 +148,26 @@ __host__ __device__ inline void cache_band(const CacheGeo* g, int layer, int shi
   *zl = lo_in;
   *zr = hi_in;
 }
-// A block of the cached layer kernel covers kCacheChunk consecutive columns
-// (output positions of a conv, input-aligned positions of a transposed conv)
-// and stages their input window in LDS.
+// A group of the cached kernel covers kCacheChunk consecutive columns at a
+// time (output positions of a conv, input-aligned positions of a transposed
+// conv) and stages their input window in LDS.
 constexpr int kCacheChunk = 64;
 // layer shapes the cached kernel takes: k7 p3 convs (stride 1 or 2) and k7
-// s2 p3 transposed convs whose C_in rounds up to a compiled channel tile
+// s2 p3 transposed convs whose C_in rounds up to a compiled channel tile (a
+// conv's window of a chunk is twice a transposed conv's, so convs stop at 32
+// input channels to keep the fused kernel's staging in registers)
 inline bool cache_layer_fits(const CacheGeo& g) {
   const int cip = (g.ci + 7) / 8 * 8;
-  const bool tile = g.type == 0 ? (cip == 8 || cip == 16 || cip == 24 || cip == 32 || cip == 64)
+  const bool tile = g.type == 0 ? (cip == 8 || cip == 16 || cip == 24 || cip == 32)
                                 : (cip == 8 || cip == 16 || cip == 32 || cip == 64);
-  return tile && g.k == 7 && g.p == 3 && (g.type == 0 || (g.s == 2 && g.op == 1));
+  // the kernel's LDS window holds a stride-1 or stride-2 conv's rows
+  return tile && g.k == 7 && g.p == 3 && (g.type == 0 ? (g.s == 1 || g.s == 2) : (g.s == 2 && g.op == 1));
 }
-// max_chunks: the largest number of chunks (left zone's plus right band's) of any item
-hipError_t launch_cache_layer(const CacheItem* items, int n, const void* arena, const CacheLayerP& P, int max_chunks,
-                              hipStream_t st);
-// noise NULL: only the clean spans (at most max_s positions per item)
-hipError_t launch_cache_emit(const CacheItem* items, int n, int W, int max_s, size_t off_noise, const float* strain,
-                             float* noise, float* clean, hipStream_t st);
+// The whole cached forward of n items (one block each: every layer's dirty
+// chunks, then the item's noise window and/or clean span; noise NULL: only
+// the clean span).
+hipError_t launch_cache_forward(const CacheItem* items, int n, const void* arena, const CacheLayerP& P,
+                                const float* strain, float* noise, float* clean, hipStream_t st);
 
 // ---- fused BBHnet (reference shape: 2 -> 32 -> 64 -> 128, k7) ----
 struct BbFusedP {

@@ -97,3 +97,16 @@ def test_oracle_agrees_outside_the_bands(W, shift):
         # than needed there)
         if zr > zl and zr + d < L:
             assert not np.array_equal(eb["a"][..., zr], ea["a"][..., zr + d]), l
+
+
+def test_layer_shapes_outside_the_cached_kernels_are_refused():
+    """The cached layer kernel stages a stride-1 or stride-2 conv's window,
+    and models take only those strides: a stride-4 conv (whose grid would
+    still divide the 16-sample shift unit) is refused up front."""
+    ok = [("conv", 21, 8, 7, 2, 3, 0, True), ("convT", 8, 8, 7, 2, 3, 1, True),
+          ("conv", 8, 1, 7, 1, 3, 0, False)]
+    assert len(gs.cache_bands(ok, 4096, 256)) == 3
+    bad = [("conv", 21, 8, 7, 4, 3, 0, True), ("convT", 8, 8, 7, 2, 3, 1, True),
+           ("convT", 8, 8, 7, 2, 3, 1, True), ("conv", 8, 1, 7, 1, 3, 0, False)]
+    with pytest.raises(gs.GwError):
+        gs.cache_bands(bad, 4096, 256)
