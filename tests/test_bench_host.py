@@ -39,15 +39,17 @@ def test_fused_kernel_accounting():
 
 
 def test_traffic_lookup_follows_the_kernel_source():
-    """The committed traffic figure is used only while the kernel source's
-    hash matches the one recorded with the counters."""
+    """Each committed traffic figure is used only while its own kernel
+    source's hash matches the one recorded with the counters."""
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic_serving_mix_bf16.json")))
-    src = open(os.path.join(ROOT, d["source"]), "rb").read()
-    got = bench.traffic_for("dc_fused_bf16")
-    if hashlib.sha256(src).hexdigest() == d["source_sha256"]:
-        assert got == d["kernels"]["dc_fused_bf16"]["bytes_per_launch"]
-    else:
-        assert got is None
+    assert "dc_fused_bf16" in d["kernels"]
+    for name, k in d["kernels"].items():
+        src = open(os.path.join(ROOT, k["source"]), "rb").read()
+        got = bench.traffic_for(name)
+        if hashlib.sha256(src).hexdigest() == k["source_sha256"]:
+            assert got == k["bytes_per_launch"], name
+        else:
+            assert got is None, name
     assert bench.traffic_for("no_such_kernel") is None
 
 
