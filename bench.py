@@ -348,16 +348,16 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn, phases=(1, 2, 
 
     Closed loop: every stream keeps one update outstanding and sends the next
     as soon as its previous result is back.  The loop is event driven: it
-    receives the next updates of the streams whose results came back,
-    launches a step after every N/P receives (N streams, P the batch
-    divisor), and polls for completed steps every 16 receives, so results
-    are taken as they finish and one batch's host work overlaps the others'
-    device work.  The clients' receives (the copies of their new samples into
-    the handed-out buffers) run on the serving thread (per-request copies of
-    tens of KB keep the interpreter lock, so receiver threads would only
-    contend for it).  Larger P: smaller, more frequent steps, lower latency.  Open loop: Poisson arrivals at the given aggregate
-    update rates.  Latency runs from a request's arrival (its samples
-    complete in memory) to its result on the host."""
+    receives the next updates of the streams whose results came back, in
+    batches of up to N/P (N streams, P the batch divisor), launches a step per
+    batch and polls for completed steps after each, so results are taken as
+    they finish and one batch's host work overlaps the others' device work.
+    A batch's receives (the copies of the clients' new samples into the
+    handed-out buffers) are one native batched copy spread over host threads
+    (gw_host_copy_batch, outside the interpreter lock).  Larger P: smaller,
+    more frequent steps, lower latency.  Open loop: Poisson arrivals at the
+    given aggregate update rates.  Latency runs from a request's arrival (its
+    samples complete in memory) to its result on the host."""
     import torch
 
     from paper_2108_12430_amd.serve import HipExecutor, Server
@@ -382,6 +382,10 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn, phases=(1, 2, 
             blocks.append((np.ascontiguousarray(src[:C, o:o + s]),
                            np.ascontiguousarray(src_s[o:o + s]) if model == "dc" else None))
         pre.append(blocks)
+
+    # the blocks' host addresses, for batched receives
+    pre_addr = [[(x.__array_interface__["data"][0], None if st is None else st.__array_interface__["data"][0])
+                 for x, st in blocks] for blocks in pre]
 
     def fill(r, i, k):
         x, st = pre[i][k % NPRE]
@@ -439,12 +443,16 @@ def serve_bench(dc, bb, prec, dc_s, bb_s, rates, seconds, log_fn, phases=(1, 2, 
             while True:
                 n = 0
                 while todo and n < per_step and not stop:
-                    i = todo.popleft()
-                    receive(srv, sids[i], i, cnt[i])
-                    cnt[i] += 1
-                    n += 1
-                    if n % 16 == 0:
-                        retire()
+                    # receive a batch: reserve, one native batched copy over
+                    # the host threads, then commit (arrival = data complete)
+                    idx = [todo.popleft() for _ in range(min(per_step - n, len(todo)))]
+                    rs = [srv.reserve(sids[i], specs[i][3]) for i in idx]
+                    srv.receive(rs, [pre_addr[i][cnt[i] % NPRE] for i in idx])
+                    for r, i in zip(rs, idx):
+                        srv.commit(r)
+                        cnt[i] += 1
+                    n += len(idx)
+                    retire()
                 if srv.pending():
                     srv.step()
                 retire()

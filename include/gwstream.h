@@ -406,6 +406,21 @@ int bbhnet_forward(const gw_model* model, gw_pool* pool, const int32_t* slots, c
                    int32_t n, int32_t W, float* logits, int32_t precision, void* ws,
                    size_t ws_bytes, void* hip_stream);
 
+/* ---- host staging --------------------------------------------------- */
+/*
+ * gw_host_copy_batch: n host-memory copies, dst[i] <- src[i] (bytes[i]
+ * bytes), spread over up to `threads` host threads (the calling thread and
+ * a pool the library starts on first use and keeps until the process ends).
+ * This is the ingest step's host side (App. B.4: requests of many streams
+ * packaged into pinned staging memory before the host-to-device copy): the
+ * serving loop packs client arrays with it, and clients receiving straight
+ * into handed-out staging buffers may use it too.  Plain host pointers;
+ * regions must not overlap.  Returns GW_EINVAL for n < 0, threads < 1 or a
+ * NULL pointer with bytes > 0; nothing is copied then.  The call returns when
+ * every copy is complete.  Thread-safe (concurrent calls are serialised).
+ */
+int gw_host_copy_batch(void* const* dst, const void* const* src, const size_t* bytes, int32_t n, int32_t threads);
+
 /* ---- measurement ------------------------------------------------------ */
 /*
  * Kernel timing for benchmarks.  Between gw_profile_begin and gw_profile_end

@@ -2,11 +2,14 @@
 // per-call item tables and kernel dispatch.  No kernel arithmetic lives here.
 #include "gwstream.h"
 
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -1935,5 +1938,106 @@ extern "C" int bbhnet_forward(const gw_model* m, gw_pool* pool, const int32_t* s
   in = reinterpret_cast<const float*>(cur);
   if (bf) return GW_OK;  // BF16: the pooling head ran in the last stage's epilogue
   LAUNCH("gap_linear", st, gw::launch_gap_linear(in, P + m->head_w, P + m->head_b, logits, n, m->c_last, L, st));
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host staging copies on a small persistent thread pool.  A call splits its
+// copies into contiguous runs of about equal bytes, one per participating
+// thread (the caller takes run 0); workers wait on a condition variable for
+// the next call's generation and report completion through a counter.  The
+// pool is created on first use and never torn down (its threads are detached
+// and idle between calls).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CopyPool {
+  std::mutex call;  // one call at a time
+  std::mutex m;
+  std::condition_variable wake, done;
+  uint64_t gen = 0;
+  int nrun = 0, pending = 0;
+  void* const* dst = nullptr;
+  const void* const* src = nullptr;
+  const size_t* bytes = nullptr;
+  std::vector<int> cut;  // run r copies items [cut[r], cut[r + 1])
+  int nworkers = 0;
+
+  void run(int r) {
+    for (int i = cut[r]; i < cut[r + 1]; ++i)
+      if (bytes[i]) std::memcpy(dst[i], src[i], bytes[i]);
+  }
+  void worker(int id) {  // takes run id + 1
+    uint64_t seen = 0;
+    for (;;) {
+      std::unique_lock<std::mutex> lk(m);
+      wake.wait(lk, [&] { return gen != seen; });
+      seen = gen;
+      const bool mine = id + 1 < nrun;
+      lk.unlock();
+      if (mine) run(id + 1);
+      lk.lock();
+      if (mine && --pending == 0) done.notify_one();
+    }
+  }
+  void ensure(int want) {
+    while (nworkers < want) {
+      std::thread(&CopyPool::worker, this, nworkers).detach();
+      ++nworkers;
+    }
+  }
+};
+
+CopyPool& copy_pool() {
+  static CopyPool* p = new CopyPool();  // never destroyed: its threads outlive static destruction
+  return *p;
+}
+
+}  // namespace
+
+extern "C" int gw_host_copy_batch(void* const* dst, const void* const* src, const size_t* bytes, int32_t n,
+                                  int32_t threads) {
+  if (n < 0 || threads < 1) return fail(GW_EINVAL, "n must be >= 0 and threads >= 1");
+  if (n == 0) return GW_OK;
+  if (!dst || !src || !bytes) return fail(GW_EINVAL, "null argument");
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (bytes[i] && (!dst[i] || !src[i])) return fail(GW_EINVAL, "null pointer with bytes > 0");
+    total += bytes[i];
+  }
+  // below ~256 KB per extra thread the wake-up costs more than it saves
+  const int nt = (int)std::max<size_t>(1, std::min<size_t>({(size_t)threads, (size_t)16, (size_t)n,
+                                                             total / (1u << 18) + 1}));
+  if (nt == 1) {
+    for (int i = 0; i < n; ++i)
+      if (bytes[i]) std::memcpy(dst[i], src[i], bytes[i]);
+    return GW_OK;
+  }
+  CopyPool& P = copy_pool();
+  std::lock_guard<std::mutex> call(P.call);
+  {
+    std::lock_guard<std::mutex> lk(P.m);
+    P.ensure(nt - 1);
+    P.dst = dst;
+    P.src = src;
+    P.bytes = bytes;
+    // runs of about total / nt bytes each
+    P.cut.assign(nt + 1, n);
+    P.cut[0] = 0;
+    size_t acc = 0;
+    int r = 1;
+    for (int i = 0; i < n && r < nt; ++i) {
+      acc += bytes[i];
+      if (acc >= total * r / nt) P.cut[r++] = i + 1;
+    }
+    for (; r < nt; ++r) P.cut[r] = n;
+    P.nrun = nt;
+    P.pending = nt - 1;
+    ++P.gen;
+  }
+  P.wake.notify_all();
+  P.run(0);
+  std::unique_lock<std::mutex> lk(P.m);
+  P.done.wait(lk, [&] { return P.pending == 0; });
   return GW_OK;
 }

@@ -33,7 +33,7 @@ EXPORTS = [
     "deepclean_backward_scratch",
     "deepclean_backward",
     "gw_bandpass_workspace", "gw_bandpass_mse", "gw_bandpass_mse_noalloc", "bbhnet_workspace", "bbhnet_forward",
-    "gw_profile_begin", "gw_profile_end",
+    "gw_host_copy_batch", "gw_profile_begin", "gw_profile_end",
 ]
 
 
@@ -88,6 +88,7 @@ def lib():
             "gw_bandpass_mse_noalloc": ([i32, i32, f32, f32, f32, vp, vp, vp, vp, vp], C.c_int),
             "bbhnet_workspace": ([vp, i32, i32, i32, P(sz)], C.c_int),
             "bbhnet_forward": ([vp, vp, vp, vp, i32, i32, vp, i32, vp, sz, vp], C.c_int),
+            "gw_host_copy_batch": ([vp, vp, vp, i32, i32], C.c_int),
             "gw_profile_begin": ([], C.c_int),
             "gw_profile_end": ([C.c_char_p, sz], C.c_int),
         }
@@ -461,6 +462,19 @@ def decimate2(*, x, taps, hist, y, stream=None):
         _f32(t, nm)
     C_, n, s = x.shape
     check(lib().gw_decimate2(n, C_, s, taps.numel(), _ptr(taps), _ptr(x), _ptr(hist), _ptr(y), _stream(stream)))
+
+
+def host_copy_batch(dst, src, nbytes, threads=8):
+    """gw_host_copy_batch: dst[i] <- src[i] (nbytes[i] bytes) for host
+    addresses given as integer sequences or uintp arrays, spread over up to
+    `threads` host threads; returns when every copy is complete.  The call
+    releases the interpreter lock."""
+    d = np.ascontiguousarray(dst, dtype=np.uintp)
+    s = np.ascontiguousarray(src, dtype=np.uintp)
+    b = np.ascontiguousarray(nbytes, dtype=np.uintp)
+    if not (d.shape == s.shape == b.shape) or d.ndim != 1:
+        raise ValueError("dst, src and nbytes must be 1-D of one length")
+    check(lib().gw_host_copy_batch(d.ctypes.data, s.ctypes.data, b.ctypes.data, int(d.size), int(threads)))
 
 
 def profile_begin():

@@ -181,6 +181,28 @@ class Server:
             self._ready[r.stream] = None
         return r
 
+    def receive(self, reqs: List[Request], sources, threads: int = 8) -> None:
+        """Copy client data into reserved requests' staging buffers with one
+        native batched copy over up to `threads` host threads (the call
+        releases the interpreter lock); commit the requests afterwards.
+        sources[k] is (samples, strain) for reqs[k]: float32 C-contiguous
+        arrays of the reserved shapes, or their host addresses as ints
+        (then the caller guarantees the sizes); strain None for BBHnet."""
+        dst, src, nb = [], [], []
+        for r, (x, st) in zip(reqs, sources):
+            xa, sa = self.ex.address(r.stage)
+            for d, a, n in ((xa, x, r.samples.nbytes), (sa, st, 0 if r.strain is None else r.strain.nbytes)):
+                if n == 0:
+                    continue
+                if not isinstance(a, int):
+                    if a.dtype != np.float32 or not a.flags.c_contiguous or a.nbytes != n:
+                        raise ValueError("source must be C-contiguous float32 of the reserved size")
+                    a = a.__array_interface__["data"][0]
+                dst.append(d)
+                src.append(a)
+                nb.append(n)
+        self.ex.copy_batch(dst, src, nb, threads)
+
     def cancel(self, r: Request) -> None:
         """Give back a reserved request's staging memory without queueing it."""
         if r.stage is not None:
@@ -263,13 +285,14 @@ class _Page:
     """One pinned staging page of a group: samples and strain regions, filled
     by bump allocation in reservation order."""
 
-    __slots__ = ("x", "s", "xn", "sn", "cx", "cs", "nx", "ns", "refs", "ev", "seq")
+    __slots__ = ("x", "s", "xn", "sn", "xa", "sa", "cx", "cs", "nx", "ns", "refs", "ev", "seq")
 
     def __init__(self, torch, nx, ns):
         self.x = torch.empty(nx, dtype=torch.float32, pin_memory=True)
         self.s = torch.empty(max(ns, 1), dtype=torch.float32, pin_memory=True)
         self.xn = self.x.numpy()
         self.sn = self.s.numpy()
+        self.xa, self.sa = self.x.data_ptr(), self.s.data_ptr()  # host addresses
         self.cx, self.cs = nx, max(ns, 1)  # capacities
         self.nx = self.ns = 0
         self.refs = 0     # reserved requests not yet launched
@@ -390,6 +413,14 @@ class HipExecutor:
     def release(self, tok):
         tok[0].refs -= 1
 
+    def address(self, tok):
+        """Host addresses of a reserved request's samples and strain."""
+        pg, ox, os_ = tok
+        return pg.xa + 4 * ox, pg.sa + 4 * os_
+
+    def copy_batch(self, dst, src, nbytes, threads=8):
+        self.gs.host_copy_batch(dst, src, nbytes, threads)
+
     def _runs(self, items, C, is_dc):
         """The launch order (page fill order) and the contiguous staging runs
         [(page, x0, nx, s0, ns)] of a group's items, or None when any item is
@@ -474,10 +505,22 @@ class HipExecutor:
         n_out = s_tot if is_dc else len(its)
         b = self._buf(key, n_f, s_tot if is_dc else 0, n_out)
         if staged is None:
-            np.concatenate([r.samples.reshape(-1) for _, r in its], out=b["h_x"].numpy()[:n_f])
+            # pack the requests into the pinned ring entry: one native batched copy
+            hx, hs = b["h_x"].data_ptr(), b["h_s"].data_ptr()
+            dst = (hx + 4 * offsets).tolist()
+            src = [r.samples.__array_interface__["data"][0] for _, r in its]
+            nbytes = (4 * sizes).tolist()
             if is_dc:
-                np.concatenate([r.strain if r.strain is not None else np.zeros(r.samples.shape[1], np.float32)
-                                for _, r in its], out=b["h_s"].numpy()[:s_tot])
+                so = np.zeros(len(its), np.int64)
+                np.cumsum(strides[:-1], out=so[1:])
+                for k, (_, r) in enumerate(its):
+                    if r.strain is not None:
+                        dst.append(hs + 4 * int(so[k]))
+                        src.append(r.strain.__array_interface__["data"][0])
+                        nbytes.append(4 * int(strides[k]))
+                    else:
+                        b["h_s"].numpy()[so[k]:so[k] + strides[k]] = 0.0
+            self.gs.host_copy_batch(dst, src, nbytes)
         ws = self._ws(key, len(its))
         with torch.cuda.stream(st):
             dx = b["d_x"][:n_f]

@@ -84,3 +84,52 @@ def test_packed_bytes_query():
     assert gs.lib().gw_model_packed_bytes(gs.MODEL_DEEPCLEAN, d.ctypes.data_as(C.c_void_p), len(d),
                                           C.byref(b)) == gs.GW_OK
     assert b.value > 0 and b.value % 256 == 0
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8, 16])
+def test_host_copy_batch(threads):
+    """gw_host_copy_batch copies every region exactly (sizes from 0 bytes to
+    a few MB, so the batch is split across the pool's threads), and refuses
+    bad arguments before copying anything."""
+    rng = np.random.default_rng(threads)
+    sizes = [0, 1, 3, 4096, 1 << 20, 12345, 3 << 20, 7] + list(rng.integers(0, 1 << 16, 40))
+    src = [rng.integers(0, 255, int(n), dtype=np.uint8) for n in sizes]
+    dst = [np.zeros(int(n), np.uint8) for n in sizes]
+    addr = lambda a: a.__array_interface__["data"][0] if a.size else 0
+    gs.host_copy_batch([addr(d) for d in dst], [addr(s) for s in src], [s.size for s in src], threads)
+    assert all(np.array_equal(d, s) for d, s in zip(dst, src))
+    keep = np.zeros(16, np.uint8)
+    for d, s, n, t in (([addr(keep)], [0], [16], threads),       # null source with bytes > 0
+                       ([addr(keep)], [addr(src[3])], [16], 0)):  # no threads
+        with pytest.raises(gs.GwError):
+            gs.host_copy_batch(d, s, n, t)
+    assert not keep.any()
+    gs.host_copy_batch([], [], [], threads)  # nothing to do
+
+
+def test_host_copy_batch_concurrent_calls():
+    """Calls from several threads at once (the interpreter lock is released
+    during each call) are serialised inside the library: every copy lands."""
+    import threading
+    rng = np.random.default_rng(7)
+    jobs = []
+    for _ in range(4):
+        src = [rng.integers(0, 255, int(n), dtype=np.uint8) for n in rng.integers(1 << 16, 1 << 20, 12)]
+        jobs.append((src, [np.zeros_like(s) for s in src]))
+    errors = []
+
+    def work(src, dst):
+        try:
+            for _ in range(10):
+                gs.host_copy_batch([d.ctypes.data for d in dst], [s.ctypes.data for s in src],
+                                   [s.size for s in src], 8)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=j) for j in jobs]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors
+    assert all(np.array_equal(d, s) for src, dst in jobs for d, s in zip(dst, src))

@@ -60,11 +60,16 @@ def serve(models, spec_idx, data, interleave_seed=None, arena=64 << 20, handout=
         model, C, W, s = SPECS[i]
         wit, strain = data[i]
         if handout:
-            # the client receives straight into the pinned staging memory
+            # the client receives straight into the pinned staging memory:
+            # by writing the views, or through the native batched copy
             r = srv.reserve(sids[i], s)
-            r.samples[...] = wit[:, k * s:(k + 1) * s]
-            if strain is not None:
-                r.strain[...] = strain[k * s:(k + 1) * s]
+            if n % 2:
+                r.samples[...] = wit[:, k * s:(k + 1) * s]
+                if strain is not None:
+                    r.strain[...] = strain[k * s:(k + 1) * s]
+            else:
+                srv.receive([r], [(np.ascontiguousarray(wit[:, k * s:(k + 1) * s]),
+                                   None if strain is None else np.ascontiguousarray(strain[k * s:(k + 1) * s]))])
             srv.commit(r)
         else:
             r = srv.submit(sids[i], wit[:, k * s:(k + 1) * s],
