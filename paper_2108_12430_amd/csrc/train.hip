@@ -673,7 +673,69 @@ __global__ __launch_bounds__(256) void bp_loss(const float* proj, int n, int nb,
   if (threadIdx.x == 0) loss[0] = (float)(s / ((double)n * W));
 }
 
-__global__ __launch_bounds__(256) void bp_grad(const float* proj, int nb, int W, int k_lo,
+// dL/dnoise[t] = scale * sum_k c_k (A_k cos_k[t] + B_k sin_k[t]).  Block
+// (x, y) covers samples [64 x, 64 x + 64) of windows [NBW y, NBW y + NBW);
+// its four waves take a quarter of the bins each (in order), evaluate each
+// bin's basis value once per sample for all of the windows, and their four
+// partial sums are added in wave order.  The windows' projections are staged
+// in LDS bin-major, [bin][window][2], so one bin's values for every window
+// are read with 16-byte loads (the same address across the wave: broadcast).
+template <int NBW>
+__global__ __launch_bounds__(256) void bp_grad(const float* proj, int n, int nb, int W, int k_lo, float scale,
+                                               float* dnoise) {
+  static_assert(NBW % 2 == 0, "two windows per 16-byte load");
+  extern __shared__ __attribute__((aligned(16))) float sp[];  // [nb][NBW][2], then [4][NBW][64] partials
+  float* red = sp + (size_t)nb * NBW * 2;
+  const int b0 = blockIdx.y * NBW, nbw = min(NBW, n - b0);
+  for (int e = threadIdx.x; e < nb * NBW; e += 256) {
+    const int kk = e / NBW, bb = e - kk * NBW;
+    const bool on = bb < nbw;
+    const int64_t o = ((int64_t)(b0 + (on ? bb : 0)) * nb + kk) * 2;
+    sp[2 * e] = on ? proj[o] : 0.0f;
+    sp[2 * e + 1] = on ? proj[o + 1] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const int k0 = nb * wave / 4, k1 = nb * (wave + 1) / 4;
+  const float twoW = 2.0f / (float)W;
+  float acc[NBW];
+#pragma unroll
+  for (int bb = 0; bb < NBW; ++bb) acc[bb] = 0.0f;
+  if (t < W) {
+    int m = (int)(((int64_t)(k_lo + k0) * t) % W);
+    for (int kk = k0; kk < k1; ++kk) {
+      float sn, cs;
+      sincospif(twoW * (float)m, &sn, &cs);
+      const float wk = bin_weight(k_lo + kk, W);
+      const float4* q = reinterpret_cast<const float4*>(sp + kk * NBW * 2);
+#pragma unroll
+      for (int j = 0; j < NBW / 2; ++j) {
+        const float4 v = q[j];  // (A, B) of windows 2j, 2j + 1
+        acc[2 * j] = fmaf(wk, fmaf(v.x, cs, v.y * sn), acc[2 * j]);
+        acc[2 * j + 1] = fmaf(wk, fmaf(v.z, cs, v.w * sn), acc[2 * j + 1]);
+      }
+      m += t;
+      if (m >= W) m -= W;
+    }
+  }
+#pragma unroll
+  for (int bb = 0; bb < NBW; ++bb) red[(wave * NBW + bb) * 64 + lane] = acc[bb];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NBW * 64; e += 256) {
+    const int bb = e >> 6, ln = e & 63, tt = blockIdx.x * 64 + ln;
+    if (bb < nbw && tt < W) {
+      float v = red[bb * 64 + ln];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) v += red[(w * NBW + bb) * 64 + ln];
+      dnoise[(int64_t)(b0 + bb) * W + tt] = scale * v;
+    }
+  }
+}
+
+// The same gradient for bands too wide to stage: one window per block, the
+// projections read from global memory.
+__global__ __launch_bounds__(256) void bp_grad_wide(const float* proj, int nb, int W, int k_lo,
                                                float scale, float* dnoise) {
   const int b = blockIdx.y;
   const int t = blockIdx.x * 256 + threadIdx.x;
@@ -706,9 +768,21 @@ hipError_t launch_bandpass(int n, int W, int k_lo, int k_hi, const float* strain
   if (nb <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bp_project, dim3(nb, n), dim3(256), 0, st, strain, noise, W, k_lo, proj);
   if (loss) hipLaunchKernelGGL(bp_loss, dim3(1), dim3(256), 0, st, proj, n, nb, W, k_lo, loss);
-  if (dnoise)
-    hipLaunchKernelGGL(bp_grad, dim3((W + 255) / 256, n), dim3(256), 0, st, proj, nb, W, k_lo,
-                       (float)(-2.0 / ((double)n * W)), dnoise);
+  if (dnoise) {
+    const float scale = (float)(-2.0 / ((double)n * W));
+    // windows per block: all of a training batch's when the projections fit
+    // in LDS, else fewer; LDS = projections + the four waves' partial sums
+    const size_t per = sizeof(float) * (2 * (size_t)nb + 4 * 64);
+    if (32 * per <= 64 * 1024)
+      hipLaunchKernelGGL(bp_grad<32>, dim3((W + 63) / 64, (n + 31) / 32), dim3(256), 32 * per, st, proj, n, nb, W,
+                         k_lo, scale, dnoise);
+    else if (2 * per <= 64 * 1024)
+      hipLaunchKernelGGL(bp_grad<2>, dim3((W + 63) / 64, (n + 1) / 2), dim3(256), 2 * per, st, proj, n, nb, W,
+                         k_lo, scale, dnoise);
+    else
+      hipLaunchKernelGGL(bp_grad_wide, dim3((W + 255) / 256, n), dim3(256), 0, st, proj, nb, W, k_lo, scale,
+                         dnoise);
+  }
   return hipGetLastError();
 }
 

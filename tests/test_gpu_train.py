@@ -62,6 +62,22 @@ def test_bandpass_loss_and_grad():
     assert rel(dn.cpu().numpy(), edn) <= 1e-5
 
 
+@pytest.mark.parametrize("n,W,f_lo,f_hi", [
+    (33, 4096, 55.0, 65.0),      # 11 bins: two window groups of the 32-window gradient kernel
+    (3, 4096, 10.0, 1500.0),     # 1491 bins: the two-window kernel
+    (2, 32768, 0.0, 2048.0),     # 16385 bins (DC and Nyquist included): the wide-band kernel
+])
+def test_bandpass_gradient_paths(n, W, f_lo, f_hi):
+    """The band-passed loss and gradient against the oracle for bands that
+    take each of the gradient kernel's paths, with ragged window groups."""
+    strain = synth.gaussian(52, (n, W))
+    noise = synth.gaussian(53, (n, W), 0.5)
+    loss, dn = gs.bandpass_mse(torch.from_numpy(strain).to(DEV), torch.from_numpy(noise).to(DEV), 4096.0, f_lo, f_hi)
+    el, edn = ref.bandpass_mse(strain, noise, 4096.0, f_lo, f_hi)
+    assert abs(loss.item() - el) <= 1e-5 * abs(el)
+    assert rel(dn.cpu().numpy(), edn) <= 1e-5
+
+
 def _train_step(m, x, strain, flags, fs=4096.0, lossfn="bandpass"):
     n, W = x.shape[0], x.shape[-1]
     xt = torch.from_numpy(x).to(DEV)
