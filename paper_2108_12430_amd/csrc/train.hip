@@ -31,6 +31,25 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   __syncthreads();
 }
 
+// Fixed-order block reduction of N doubles per thread over 256 lanes: the
+// same pairing tree as block_sum2 for every value, all values per round.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N]) {
+  __shared__ double sv[N][256];
+#pragma unroll
+  for (int j = 0; j < N; ++j) sv[j][threadIdx.x] = v[j];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int j = 0; j < N; ++j) sv[j][threadIdx.x] += sv[j][threadIdx.x + w];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = sv[j][0];
+  __syncthreads();
+}
+
 enum RMode { R_STATS = 0, R_BNBWD = 1, R_SUM = 2 };
 
 struct RedP {
@@ -631,29 +650,55 @@ hipError_t launch_wgrad(const float* P, int Ca, int Lp, const float* Q, int Cc, 
 // index advances by a constant per step (one compare and subtract) instead
 // of a 64-bit division per sample.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void bp_project(const float* strain, const float* noise, int W,
+// Projections A_k, B_k: block (x, y) takes bins [NB x, NB x + NB) of windows
+// [NBW y, NBW y + NBW), so each residual sample is read once per NB bins
+// and each basis value evaluated once per NBW windows.  A thread keeps FP64
+// running sums over samples t = tid, tid + 256, ... for every (window, bin)
+// of the block; one fixed block tree adds the threads' sums.
+template <int NBW, int NB>
+__global__ __launch_bounds__(256) void bp_project(const float* strain, const float* noise, int n, int nb, int W,
                                                   int k_lo, float* proj) {
-  const int b = blockIdx.y, kk = blockIdx.x, k = k_lo + kk;
-  const float* sr = strain + (int64_t)b * W;
-  const float* nr = noise + (int64_t)b * W;
-  double sa = 0.0, sb = 0.0;
+  const int kb = blockIdx.x * NB, nbk = min(NB, nb - kb);
+  const int b0 = blockIdx.y * NBW, nbw = min(NBW, n - b0);
+  double acc[2 * NBW * NB];  // (A, B) of (window bb, bin q) at 2 (bb NB + q)
+#pragma unroll
+  for (int j = 0; j < 2 * NBW * NB; ++j) acc[j] = 0.0;
   const float twoW = 2.0f / (float)W;
-  // m = k t mod W for t = threadIdx.x, threadIdx.x + 256, ...
-  int m = (int)(((int64_t)k * threadIdx.x) % W);
-  const int step = (int)(((int64_t)k * 256) % W);
-  for (int t = threadIdx.x; t < W; t += 256) {
-    const float r = sr[t] - nr[t];
-    float sn, cs;
-    sincospif(twoW * (float)m, &sn, &cs);
-    sa += (double)(r * cs);
-    sb += (double)(r * sn);
-    m += step;
-    if (m >= W) m -= W;
+  // m[q] = (k_lo + kb + q) t mod W for t = threadIdx.x, threadIdx.x + 256, ...
+  int m[NB], step[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int64_t k = k_lo + kb + q;
+    m[q] = (int)((k * threadIdx.x) % W);
+    step[q] = (int)((k * 256) % W);
   }
-  block_sum2(sa, sb);
-  if (threadIdx.x == 0) {
-    proj[((int64_t)b * gridDim.x + kk) * 2 + 0] = (float)sa;
-    proj[((int64_t)b * gridDim.x + kk) * 2 + 1] = (float)sb;
+  for (int t = threadIdx.x; t < W; t += 256) {
+    float r[NBW];
+#pragma unroll
+    for (int bb = 0; bb < NBW; ++bb) {
+      const int64_t o = (int64_t)(b0 + (bb < nbw ? bb : 0)) * W + t;
+      r[bb] = strain[o] - noise[o];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      float sn, cs;
+      sincospif(twoW * (float)m[q], &sn, &cs);
+#pragma unroll
+      for (int bb = 0; bb < NBW; ++bb) {
+        acc[2 * (bb * NB + q)] += (double)(r[bb] * cs);
+        acc[2 * (bb * NB + q) + 1] += (double)(r[bb] * sn);
+      }
+      m[q] += step[q];
+      if (m[q] >= W) m[q] -= W;
+    }
+  }
+  block_sum_n(acc);
+  if (threadIdx.x < NBW * NB) {
+    const int bb = threadIdx.x / NB, q = threadIdx.x - bb * NB;
+    if (bb < nbw && q < nbk) {
+      proj[((int64_t)(b0 + bb) * nb + kb + q) * 2 + 0] = (float)acc[2 * (bb * NB + q)];
+      proj[((int64_t)(b0 + bb) * nb + kb + q) * 2 + 1] = (float)acc[2 * (bb * NB + q) + 1];
+    }
   }
 }
 
@@ -766,7 +811,9 @@ hipError_t launch_bandpass(int n, int W, int k_lo, int k_hi, const float* strain
                            hipStream_t st) {
   const int nb = k_hi - k_lo + 1;
   if (nb <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(bp_project, dim3(nb, n), dim3(256), 0, st, strain, noise, W, k_lo, proj);
+  constexpr int PW = 4, PB = 1;  // windows and bins per projection block
+  hipLaunchKernelGGL((bp_project<PW, PB>), dim3((nb + PB - 1) / PB, (n + PW - 1) / PW), dim3(256), 0, st, strain,
+                     noise, n, nb, W, k_lo, proj);
   if (loss) hipLaunchKernelGGL(bp_loss, dim3(1), dim3(256), 0, st, proj, n, nb, W, k_lo, loss);
   if (dnoise) {
     const float scale = (float)(-2.0 / ((double)n * W));
