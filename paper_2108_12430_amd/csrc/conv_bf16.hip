@@ -990,15 +990,27 @@ constexpr int mn(int a, int b) { return a < b ? a : b; }
 // 8-channel layers: the valid accumulator rows sit in lanes 0..31, so two
 // column tiles share one epilogue pass (lanes 32..63 take the second tile)
 constexpr bool COMPACT(int l) { return l < 8 && !STACK(l) && MT(l) == 1 && cip(C[l + 1]) == 8; }
-// column tiles per work unit: enough that every layer is one round of units
-// (times GW_FUSED_NTCMUL, at most 4)
-#ifndef GW_FUSED_NTCMUL
-#define GW_FUSED_NTCMUL 1
-#endif
+// A work unit holds at most FMAX weight fragments (32 VGPRs), so all of its
+// fragments are requested at once and the next layer's can be requested
+// while this layer's epilogue runs.  Layers with more (phase, channel tile)
+// pairs x K steps than that split the pairs over SPL units; the others keep
+// every pair in one unit.  Compact and stacked layers have a single pair.
+constexpr int FMAX = 8;
+constexpr int SPL(int l) {
+  return COMPACT(l) || STACK(l) || QP(l) * KS(l) <= FMAX ? 1 : QP(l) / 2 * KS(l) <= FMAX && QP(l) % 2 == 0 ? 2 : 4;
+}
+// column tiles per work unit: enough that every layer is one round of at
+// most NW units (at most 4)
 constexpr int NTC(int l) {
-  return COMPACT(l) ? mn(4, 2 * cdiv(NT(l), 2 * NW) * GW_FUSED_NTCMUL) : mn(4, cdiv(NT(l), NW) * GW_FUSED_NTCMUL);
+  return COMPACT(l) ? mn(4, 2 * cdiv(NT(l), 2 * NW)) : mn(4, cdiv(NT(l), NW / SPL(l)));
 }
 constexpr int NG(int l) { return cdiv(NT(l), NTC(l)); }
+constexpr int NU(int l) { return TOEP(l) ? TB : NG(l) * SPL(l); }              // units of layer l
+constexpr int NF(int l) { return TOEP(l) ? KS8 : QP(l) / SPL(l) * KS(l); }   // fragments per unit
+// fragments requested during the previous layer: at most 7, so that the
+// request fits beside that layer's epilogue without spilling; a unit's
+// remaining fragment (the last its MFMAs read) is requested as it starts
+constexpr int PF(int l) { return NF(l) < 7 ? NF(l) : 7; }
 // per-layer table of B-fragment row offsets: KOFF[l][lg][ks] (elements) for
 // the 8 channels at kappa = 32 ks + 8 lg, i.e. tap jj = kappa / C_in and
 // channel i0 = kappa mod C_in; taps past the kernel (zero weights) read tap
@@ -1009,17 +1021,10 @@ __host__ __device__ constexpr int koff(int l, int lg, int ks) {
   const int j = jj < KT(l) ? jj : KT(l) - 1;
   return phys(l, j) * rs(C[l]) + i0;
 }
-// the (phase, channel tile) pairs of a layer with few column groups are
-// split over SPL waves
-#ifndef GW_FUSED_MAXSPL
-#define GW_FUSED_MAXSPL 2
-#endif
-constexpr int SPL(int l) {
-  return COMPACT(l) || STACK(l) ? 1
-         : GW_FUSED_MAXSPL >= 4 && QP(l) % 4 == 0 && NG(l) * 4 <= NW
-             ? 4
-             : (GW_FUSED_MAXSPL >= 2 && QP(l) % 2 == 0 && NG(l) * 2 <= NW ? 2 : 1);
+constexpr bool units_fit(int l) {
+  return l == 9 || (NU(l) <= NW && NF(l) <= FMAX && QP(l) % SPL(l) == 0 && units_fit(l + 1));
 }
+static_assert(units_fit(0), "every layer is one round of units of at most FMAX fragments");
 }  // namespace fused
 
 // Two floats -> packed bf16 pair, first in the low half: the hardware
@@ -1161,27 +1166,52 @@ __device__ __forceinline__ void fused_epi(const f32x4 (&acc)[NTCl][Q], int nt0, 
 
 // One layer of the fused network: LDS in -> LDS out (or global for the last).
 // Work units are (group of NTC column tiles, share of the (phase, channel
-// tile) pairs); unit u goes to wave u mod NW.  A unit requests all of its
-// weight fragments (at most 16, 64 VGPRs) from global memory before its first
-// MFMA; the 92 KB of packed weights stay in L2, shared by every block.  kt
-// holds the layer's row of the B-offset table.
+// tile) pairs); every layer has at most NW units and unit u runs on wave u.
+// The 92 KB of packed weights stay in L2, shared by every block; a unit's
+// fragments (at most FMAX) arrive in wf, requested while the previous
+// layer's epilogue ran, and once its MFMAs have read them the wave requests
+// its fragments of the next layer into the same registers.  kt holds the
+// layer's row of the B-offset table.
+//
+// Request wave `wave`'s weight fragments [I0, I1) of layer l into wf:
+// fragment i = k KS + ks (pair q = sp + k SPL, K step ks) of unit `wave`,
+// sp = wave mod SPL, at [q][ks][lane] in the layer's pack (the output conv:
+// fragment ks at [ks][lane]).
+template <int l, int I0, int I1>
+__device__ __forceinline__ void fused_frags(u32x4 (&wf)[fused::FMAX], const uint4* wg, int wave, int lane) {
+  using namespace fused;
+  if (I0 >= I1 || wave >= NU(l)) return;  // wave-uniform
+  const u32x4* wq = reinterpret_cast<const u32x4*>(wg) + lane;
+  if constexpr (TOEP(l)) {
+#pragma unroll
+    for (int ks = I0; ks < I1; ++ks) wf[ks] = wq[ks * 64];
+  } else {
+    constexpr int KSn = KS(l), SP = SPL(l);
+    const int sp = wave % SP;
+#pragma unroll
+    for (int i = I0; i < I1; ++i) wf[i] = wq[(sp * KSn + (i / KSn) * SP * KSn + i % KSn) * 64];
+  }
+}
+
 // The output conv as a Toeplitz product (see TOEP): wave w < TB computes
 // outputs [256 w, 256 w + 256) of the tile with KS8 MFMAs whose A operand
 // (8 channels at one time offset per lane) comes from LDS and whose B
 // operand (the banded weights) from the packed fragments; the epilogue
-// writes the noise and the fully-online clean output.
+// writes the noise and the fully-online clean output.  The fragments of the
+// next tile's first layer are requested after the MFMAs (wgn).
 template <bool F16>
-__device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, const uint4* wg, const float* ksc,
-                                               const float* ksh, int pos0, const ConvP* op, int b, int Wout) {
+__device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, u32x4 (&wf)[fused::FMAX],
+                                               const uint4* wgn, const float* ksc, const float* ksh, int pos0,
+                                               const ConvP* op, int b, int Wout) {
   using namespace fused;
   constexpr int RSI = rs(C[8]);
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lc = lane & 15, lg = lane >> 4;
-  if (wave >= TB) return;  // wave-uniform
-  const u32x4* wq = reinterpret_cast<const u32x4*>(wg) + lane;
-  u32x4 wf[KS8];
-#pragma unroll
-  for (int ks = 0; ks < KS8; ++ks) wf[ks] = wq[ks * 64];
+  static_assert(PF(8) == NF(8), "the output conv's fragments all arrive with the previous layer");
+  if (wave >= TB) {  // wave-uniform
+    fused_frags<0, 0, PF(0)>(wf, wgn, wave, lane);
+    return;
+  }
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < KS8; ++ks) {
@@ -1192,6 +1222,7 @@ __device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, cons
     const uint4 av = *reinterpret_cast<const uint4*>(in + prow8(r) * RSI);
     acc = mfma16<F16>(av, __builtin_bit_cast(uint4, wf[ks]), acc);
   }
+  fused_frags<0, 0, PF(0)>(wf, wgn, wave, lane);
   // D[m = 4 lg + q][n = lc]: output 16 m + n of this wave's 256
   const float sc = ksc[0], sh = ksh[0];
 #pragma unroll
@@ -1212,9 +1243,10 @@ __device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, cons
 }
 
 template <int l, bool F16>
-__device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
-                                               const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
-                                               const ConvP* op, int b, int Wout) {
+__device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint16_t* out, u32x4 (&wf)[fused::FMAX],
+                                               const uint4* wg, const uint4* wgn, const int* kt, const float* ksc,
+                                               const float* ksh, int pos0, int Lout, const ConvP* op, int b,
+                                               int Wout) {
   using namespace fused;
   constexpr int RSI = rs(C[l]);
   constexpr int KSn = KS(l), NTn = NT(l);
@@ -1235,16 +1267,15 @@ __device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint
   }
   // window-edge tiles store zeros outside the signal
   const bool edge = pos0 < 0 || pos0 + NR[l + 1] > Lout;
-  for (int unit = wave; unit < NG(l) * SP; unit += NW) {
+  if (wave >= NU(l)) {  // wave-uniform
+    fused_frags<l + 1, 0, PF(l + 1)>(wf, wgn, wave, lane);
+    return;
+  }
+  fused_frags<l, PF(l), NF(l)>(wf, wg, wave, lane);
+  {
+    const int unit = wave;
     const int nt0 = (unit / SP) * NTCl, sp = unit % SP;  // wave-uniform
     const uint16_t* colbase = in + ((nt0 * 16 + lc) * SX) * RSI;
-    // fragment (pair q = sp + k SP = ph * M + mt, K step ks) of this lane
-    const u32x4* wq = reinterpret_cast<const u32x4*>(wg) + sp * KSn * 64 + lane;
-    u32x4 af[Q][KSn];
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-#pragma unroll
-      for (int ks = 0; ks < KSn; ++ks) af[k][ks] = wq[(k * SP * KSn + ks) * 64];
     f32x4 acc[NTCl][Q];
 #pragma unroll
     for (int a = 0; a < NTCl; ++a)
@@ -1253,14 +1284,21 @@ __device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint
 #pragma unroll
     for (int ks = 0; ks < KSn; ++ks) {
       const uint16_t* src = colbase + ko[ks];
+      // the K step's B fragments of every column tile, read together; tiles
+      // past the layer's last re-read that one (their sums are never stored)
+      uint4 bb[NTCl];
 #pragma unroll
       for (int a = 0; a < NTCl; ++a) {
-        if (nt0 + a >= NTn) break;  // wave-uniform
-        const uint4 bb = *reinterpret_cast<const uint4*>(src + a * 16 * SX * RSI);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) acc[a][k] = mfma16<F16>(__builtin_bit_cast(uint4, af[k][ks]), bb, acc[a][k]);
+        const int aa = a < NTn - nt0 ? a : NTn - 1 - nt0;  // wave-uniform
+        bb[a] = *reinterpret_cast<const uint4*>(src + aa * 16 * SX * RSI);
       }
+#pragma unroll
+      for (int a = 0; a < NTCl; ++a)
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          acc[a][k] = mfma16<F16>(__builtin_bit_cast(uint4, wf[k * KSn + ks]), bb[a], acc[a][k]);
     }
+    fused_frags<l + 1, 0, PF(l + 1)>(wf, wgn, wave, lane);
     if (edge)
       fused_epi<l, true, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
     else
@@ -1269,13 +1307,13 @@ __device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint
 }
 
 template <int l, bool F16>
-__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, const uint4* wg,
-                                            const int* kt, const float* ksc, const float* ksh, int pos0, int Lout,
-                                            const ConvP* op, int b, int Wout) {
+__device__ __forceinline__ void fused_layer(int tid, const uint16_t* in, uint16_t* out, u32x4 (&wf)[fused::FMAX],
+                                            const uint4* wg, const uint4* wgn, const int* kt, const float* ksc,
+                                            const float* ksh, int pos0, int Lout, const ConvP* op, int b, int Wout) {
   if constexpr (fused::TOEP(l))
-    fused_toeplitz<F16>(tid, in, wg, ksc, ksh, pos0, op, b, Wout);
+    fused_toeplitz<F16>(tid, in, wf, wgn, ksc, ksh, pos0, op, b, Wout);
   else
-    fused_layer_mm<l, F16>(tid, in, out, wg, kt, ksc, ksh, pos0, Lout, op, b, Wout);
+    fused_layer_mm<l, F16>(tid, in, out, wf, wg, wgn, kt, ksc, ksh, pos0, Lout, op, b, Wout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1363,9 +1401,10 @@ __device__ __forceinline__ void load_chunk(u32x4 (&d)[XRaw<IN>::NV], const uint1
   }
 }
 
-// Issue the loads of a tile's input rows [q0, q0 + XROWS) of window b.
+// Issue the loads of a tile's input rows [q0, q0 + XROWS) of window b
+// (tid: the thread index).
 template <int IN>
-__device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q0) {
+__device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q0, int tid) {
   using namespace fused;
   const int Ci = p.Ci, Lin = p.Lin;
   const int qa = q0 - (((q0 % 8) + 8) % 8);
@@ -1392,7 +1431,7 @@ __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q
   }
 #pragma unroll
   for (int it = 0; it < XITEMS; ++it) {
-    const int e = threadIdx.x + NTHR * it;
+    const int e = tid + NTHR * it;
     const int g = e % XG, ch = e / XG;
     const int qc = qa + 8 * ch;
 #pragma unroll
@@ -1408,7 +1447,7 @@ __device__ __forceinline__ void load_x(XRaw<IN>& R, const ConvP& p, int b, int q
 
 // Write the staged rows to LDS (row stride RS, split by row residue mod 4).
 template <int IN, bool F16>
-__device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q0) {
+__device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q0, int tid) {
   static_assert(!(F16 && IN == IN_RING), "the ring's 16-bit shadow is BF16");
   using namespace fused;
   constexpr int RS = rs(C[0]), ROWS = XROWS;
@@ -1417,7 +1456,7 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
   const int nch = (q0 + ROWS - qa + 7) / 8;
 #pragma unroll
   for (int it = 0; it < XITEMS; ++it) {
-    const int e = threadIdx.x + NTHR * it;
+    const int e = tid + NTHR * it;
     const int g = e % XG, ch = e / XG;
     if (ch >= nch) continue;
     // bf16 pairs of each channel: c[k][d] holds samples 2d, 2d+1
@@ -1474,7 +1513,10 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
   if (t0 >= t1) return;  // block-uniform
 
   XRaw<IN> raw;
-  load_x<IN>(raw, p, t0 / tpw, (t0 % tpw) * T + LO[0]);
+  load_x<IN>(raw, p, t0 / tpw, (t0 % tpw) * T + LO[0], threadIdx.x);
+  u32x4 wf[FMAX];  // this wave's weight fragments of the current layer
+  fused_frags<0, 0, PF(0)>(wf, reinterpret_cast<const uint4*>(f.wpk[0]),
+                           __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), threadIdx.x & 63);
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
     if (threadIdx.x < 64) {
@@ -1489,7 +1531,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     }
   }
   // input tile rows [u0 - 93, u0 + T + 93) in [time][channel] layout
-  store_x<IN, F16>(bufA, raw, (t0 % tpw) * T + LO[0]);
+  store_x<IN, F16>(bufA, raw, (t0 % tpw) * T + LO[0], threadIdx.x);
   __syncthreads();
 
   for (int t = t0; t < t1; ++t) {
@@ -1503,8 +1545,9 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
     {                                                                                                       \
       int tid = threadIdx.x;                                                                                \
       asm volatile("" : "+v"(tid));                                                                         \
-      fused_layer<l, F16>(tid, IN_BUF, OUT_BUF, reinterpret_cast<const uint4*>(f.wpk[l]), &ktab[l][0][0],       \
-                     ksc[l], ksh[l], u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);             \
+      fused_layer<l, F16>(tid, IN_BUF, OUT_BUF, wf, reinterpret_cast<const uint4*>(f.wpk[l]),               \
+                          reinterpret_cast<const uint4*>(f.wpk[(l + 1) % 9]), &ktab[l][0][0], ksc[l], ksh[l],  \
+                          u0 / (SCALE_DIV) + LO[l + 1], W / (SCALE_DIV), &p, b, W);                         \
       __syncthreads();                                                                                      \
     }
     GW_FUSED_LAYER(0, bufA, bufB, 2)
@@ -1519,9 +1562,12 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
 #undef GW_FUSED_LAYER
     if (more) {
       // the next tile's input: the other block on the CU hides its latency
+      // (an opaque copy of the thread index, as for the layers)
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
       const int nq = ((t + 1) % tpw) * T + LO[0];
-      load_x<IN>(raw, p, (t + 1) / tpw, nq);
-      store_x<IN, F16>(bufA, raw, nq);
+      load_x<IN>(raw, p, (t + 1) / tpw, nq, tid);
+      store_x<IN, F16>(bufA, raw, nq, tid);
       __syncthreads();
     }
   }
