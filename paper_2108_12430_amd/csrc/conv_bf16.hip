@@ -1223,6 +1223,7 @@ __device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, u32x
     acc = mfma16<F16>(av, __builtin_bit_cast(uint4, wf[ks]), acc);
   }
   fused_frags<0, 0, PF(0)>(wf, wgn, wave, lane);
+  __builtin_amdgcn_s_setprio(1);  // epilogue ahead of MFMA chains, as in fused_layer_mm
   // D[m = 4 lg + q][n = lc]: output 16 m + n of this wave's 256
   const float sc = ksc[0], sh = ksh[0];
 #pragma unroll
@@ -1240,6 +1241,7 @@ __device__ __forceinline__ void fused_toeplitz(int tid, const uint16_t* in, u32x
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 template <int l, bool F16>
@@ -1299,10 +1301,14 @@ __device__ __forceinline__ void fused_layer_mm(int tid, const uint16_t* in, uint
           acc[a][k] = mfma16<F16>(__builtin_bit_cast(uint4, wf[k * KSn + ks]), bb[a], acc[a][k]);
     }
     fused_frags<l + 1, 0, PF(l + 1)>(wf, wgn, wave, lane);
+    // a layer ends when its slowest wave's epilogue does: waves in their
+    // epilogue issue ahead of waves still in their MFMA chains
+    __builtin_amdgcn_s_setprio(1);
     if (edge)
       fused_epi<l, true, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
     else
       fused_epi<l, false, NTCl, Q, F16>(acc, nt0, sp, lc, lg, out, ksc, ksh, pos0, Lout, op, b, Wout);
+    __builtin_amdgcn_s_setprio(0);
   }
 }
 
@@ -1566,8 +1572,10 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
       int tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
       const int nq = ((t + 1) % tpw) * T + LO[0];
+      __builtin_amdgcn_s_setprio(2);  // ahead of the other block's epilogues
       load_x<IN>(raw, p, (t + 1) / tpw, nq, tid);
       store_x<IN, F16>(bufA, raw, nq, tid);
+      __builtin_amdgcn_s_setprio(0);
       __syncthreads();
     }
   }
