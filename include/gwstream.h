@@ -127,6 +127,21 @@ int gw_stream_info(const gw_pool* pool, int32_t slot, int32_t* C, int32_t* W, in
  * NULL.  Used to export stream state and by tests.
  */
 int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_t* out_bf16, void* hip_stream);
+/*
+ * gw_stream_load (App. B.1, the snapshotter's state): restore a slot from an
+ * exported snapshot, e.g. to move a stream to another pool or process.
+ *   window  device [C][W] float32, oldest sample first (the layout that
+ *           gw_stream_window writes), read on hip_stream
+ *   n_seen  samples the stream had received (gw_stream_info of the source)
+ * The slot's ring becomes that window (its BF16 shadow re-derived by round
+ * to nearest even, so both equal the exported ones bitwise), its head 0 and
+ * its received count n_seen; an attached activation cache is invalidated
+ * (the next cached forward recomputes every position).  Later updates and
+ * forwards continue exactly as on the source slot.  Ordering with other work
+ * on the slot is as for snapshot_update.  Errors: GW_EINVAL (bad slot, null
+ * window, negative n_seen), GW_EHIP.
+ */
+int gw_stream_load(gw_pool* pool, int32_t slot, const float* window, int64_t n_seen, void* hip_stream);
 /* Pool occupancy: bytes in use by rings and bytes still free for rings. */
 int gw_pool_usage(const gw_pool* pool, size_t* used, size_t* free_bytes);
 

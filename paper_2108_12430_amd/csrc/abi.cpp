@@ -454,6 +454,34 @@ extern "C" int gw_stream_window(gw_pool* pool, int32_t slot, float* out, uint16_
   return GW_OK;
 }
 
+extern "C" int gw_stream_load(gw_pool* pool, int32_t slot, const float* window, int64_t n_seen, void* hip_stream) {
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  CHK(pool->check_slot(slot));
+  if (!window) return fail(GW_EINVAL, "null window");
+  if (n_seen < 0) return fail(GW_EINVAL, "negative n_seen");
+  auto& s = pool->slots[slot];
+  // one update of W samples written from ring position 0: the ring holds the
+  // window oldest first and the head returns to 0
+  std::vector<Item> items(1);
+  std::memset(&items[0], 0, sizeof(Item));
+  items[0].ring = pool->ring_elem(s);
+  items[0].shadow = pool->shadow_elem(s);
+  items[0].src = 0;
+  items[0].head = 0;
+  items[0].s = s.W;
+  items[0].C = s.C;
+  items[0].W = s.W;
+  const Item* dev = nullptr;
+  StageGuard guard;
+  CHK(pool->stager.stage(items, S(hip_stream), &dev, &guard));
+  pool->mark_used(&slot, 1, guard);
+  LAUNCH("snapshot", S(hip_stream), gw::launch_snapshot(pool->arena, dev, 1, s.C * s.W, window, S(hip_stream)));
+  s.head = 0;
+  s.n_seen = n_seen;
+  s.cache_valid = false;
+  return GW_OK;
+}
+
 extern "C" int gw_pool_usage(const gw_pool* pool, size_t* used, size_t* free_bytes) {
   if (!pool) return fail(GW_EINVAL, "null pool");
   size_t f = 0;

@@ -25,7 +25,7 @@ _CODES = {1: "GW_EINVAL", 2: "GW_ENOMEM", 3: "GW_ESTATE", 4: "GW_EHIP", 5: "GW_E
 
 EXPORTS = [
     "gw_last_error", "gw_pool_init", "gw_pool_free", "gw_stream_open", "gw_stream_close",
-    "gw_stream_info", "gw_stream_window", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
+    "gw_stream_info", "gw_stream_window", "gw_stream_load", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
     "gw_model_set_layerwise",
     "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
@@ -65,6 +65,7 @@ def lib():
             "gw_stream_info": ([vp, i32, P(i32), P(i32), P(i64)], C.c_int),
             "gw_pool_usage": ([vp, P(sz), P(sz)], C.c_int),
             "gw_stream_window": ([vp, i32, vp, vp, vp], C.c_int),
+            "gw_stream_load": ([vp, i32, vp, i64, vp], C.c_int),
             "snapshot_update": ([vp, i32, vp, vp, vp, vp, vp], C.c_int),
             "gw_model_packed_bytes": ([i32, vp, i32, P(sz)], C.c_int),
             "gw_model_create": ([i32, vp, i32, vp, i64, vp, sz, vp, P(vp)], C.c_int),
@@ -198,6 +199,16 @@ class Pool:
             out = torch.empty((c, w), dtype=torch.float32, device=self.device)
             check(lib().gw_stream_window(self.h, slot, _ptr(out), None, _stream(stream)))
         return out
+
+    def load(self, slot, window, n_seen, stream=None):
+        """gw_stream_load: restore a slot from an exported [C][W] float32
+        device window (oldest sample first, as window() returns it) and the
+        source's received-sample count."""
+        _f32(window, "window")
+        c, w, _ = self.info(slot)
+        if tuple(window.shape) != (c, w):
+            raise ValueError(f"window must be [{c}][{w}]")
+        check(lib().gw_stream_load(self.h, slot, _ptr(window), int(n_seen), _stream(stream)))
 
     def attach_cache(self, slot, cache):
         """gw_stream_attach_cache: a uint8 device tensor (or None to detach)

@@ -181,6 +181,51 @@ def test_pool_admission_and_errors():
     assert np.all(pool.window(c).cpu().numpy() == 0)         # and starts from zeros
 
 
+def test_stream_restore_continues_bitwise(dc):
+    """A stream exported with gw_stream_window / gw_stream_info and restored
+    into another slot with gw_stream_load continues bitwise like the source:
+    the same window, BF16 shadow and count, then the same forward outputs
+    (FP32 and BF16) after further updates applied to both.  The source's
+    head is unaligned (odd strides) and the restored head is 0, so the ring
+    reads of the two slots take different paths."""
+    m, _, _ = dc
+    C_, W = 21, 4096
+    stream = synth.gaussian(41, (C_, 9000))
+    strain = synth.gaussian(42, (1, 9000))[0]
+    pool = gs.Pool(1 << 26, max_slots=4, max_items=4)
+    a = pool.open(C_, W)
+    pos = 0
+    for s in [300, 37, 512, 1000, 64, 129, 2048]:
+        pool.update([a], [s], torch.from_numpy(np.ascontiguousarray(stream[:, pos:pos + s])).to(DEV).reshape(-1), [0])
+        pos += s
+    win = pool.window(a)
+    n_seen = pool.info(a)[2]
+    b = pool.open(C_, W)
+    pool.load(b, win, n_seen)
+    assert pool.info(b) == pool.info(a)
+    assert torch.equal(pool.window(b), win)
+    assert torch.equal(pool.window(b, bf16=True), pool.window(a, bf16=True))
+    for s in [256, 77, 1024]:
+        blk = np.ascontiguousarray(stream[:, pos:pos + s]).reshape(-1)
+        pool.update([a, b], [s, s], torch.from_numpy(np.concatenate([blk, blk])).to(DEV), [0, C_ * s])
+        st = torch.from_numpy(np.tile(strain[pos:pos + s], 2).astype(np.float32)).to(DEV)
+        pos += s
+        for prec in (gs.FP32, gs.BF16):
+            noise = torch.empty((2, W), device=DEV)
+            clean = torch.empty(2 * s, device=DEV)
+            m.forward(pool=pool, slots=[a, b], W=W, strides=[s, s], strain=st, noise=noise, clean=clean,
+                      precision=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(noise[0], noise[1]), (s, prec)
+            assert torch.equal(clean[:s], clean[s:]), (s, prec)
+    assert torch.equal(pool.window(a), pool.window(b))
+    with pytest.raises(ValueError):                          # shape checked by the binding
+        pool.load(b, win[:, :100].contiguous(), 0)
+    with pytest.raises(gs.GwError) as e:                     # negative count
+        pool.load(b, win, -1)
+    assert e.value.code == gs.GW_EINVAL
+
+
 # --------------------------------------------------------------------------- streaming
 
 def test_streaming_8s_window_fp32(dc):
