@@ -187,7 +187,9 @@ int snapshot_update(gw_pool* pool, int32_t n, const int32_t* slots, const int32_
  * tiles).  gw_model_create validates `desc` and `n_params`, keeps pointers to
  * `dev_params` (which must outlive the model) and enqueues the packing
  * kernels on `hip_stream`.  After the caller changes dev_params (a training
- * step), gw_model_refresh re-derives the packed data.
+ * step), gw_model_refresh re-derives the packed data; activation caches
+ * computed with the previous weights are then recomputed in full by their
+ * next deepclean_forward_cached.
  */
 int gw_model_packed_bytes(int32_t kind, const int32_t* desc, int32_t desc_len, size_t* bytes);
 int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_len, const float* dev_params,
@@ -291,7 +293,8 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
  * hip_stream, bring every cache to the current window and write the outputs.
  * A cache that holds the window from `a` samples ago, a a multiple of 16
  * below W, is updated incrementally (its dirty bands only); any other cache
- * (never computed, attached anew, a not a multiple of 16 or a >= W), and
+ * (never computed, attached anew, computed by another model or before this
+ * model's last gw_model_refresh, a not a multiple of 16 or a >= W), and
  * every cache under GW_CACHE_FULL, is recomputed at every position.  Each
  * value is the same function of its inputs either way, so the two are
  * bitwise equal.  Arithmetic: BF16 activations (the snapshot's BF16 shadow

@@ -226,6 +226,8 @@ struct gw_pool {
     bool cache_valid = false;  // holds the window that ended cache_seen samples into the stream
     int cache_T = 0;           // its window start modulo W (ring heads)
     int64_t cache_seen = 0;
+    const void* cache_model = nullptr;  // the model and weight generation that computed it
+    uint64_t cache_gen = 0;
   };
   // A closed slot's region whose last users may still be running: a later
   // open that reuses any of its bytes orders its zero-fill after them.
@@ -562,6 +564,7 @@ constexpr int DENSE_ITEMS = 4096;  // item-table capacity for dense-input calls
 
 struct gw_model {
   int kind = 0;
+  uint64_t gen = 0;  // weight generation: counts gw_model_refresh calls
   std::vector<LayerD> layers;
   std::vector<StageD> stages;
   int c_in = 0, c_last = 0;
@@ -898,6 +901,7 @@ extern "C" int gw_model_create(int32_t kind, const int32_t* desc, int32_t desc_l
 
 extern "C" int gw_model_refresh(gw_model* m, void* hip_stream) {
   if (!m) return fail(GW_EINVAL, "null model");
+  ++m->gen;  // activation caches computed with the previous weights are recomputed in full
   return pack_model(m, S(hip_stream));
 }
 
@@ -1345,7 +1349,8 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     it.shadow = pool->shadow_elem(sl);
     it.in_head = sl.head;  // oldest sample of the current window
     const int64_t adv = sl.n_seen - sl.cache_seen;
-    if (!sl.cache_valid || (flags & GW_CACHE_FULL) || adv < 0 || adv >= W || adv % 16) {
+    if (!sl.cache_valid || sl.cache_model != m || sl.cache_gen != m->gen || (flags & GW_CACHE_FULL) || adv < 0 ||
+        adv >= W || adv % 16) {
       it.shift = -1;
       it.T = 0;
     } else {
@@ -1383,6 +1388,8 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     sl.cache_valid = true;
     sl.cache_T = items[i].T;
     sl.cache_seen = sl.n_seen;
+    sl.cache_model = m;
+    sl.cache_gen = m->gen;
   }
   return GW_OK;
 }

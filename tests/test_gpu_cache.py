@@ -141,6 +141,34 @@ def test_streams_independent_of_batch_and_fallbacks(model):
         assert np.array_equal(n1, n2) and np.array_equal(c1, c2), (s, skip, reattach)
 
 
+def test_refresh_recomputes_caches():
+    """After gw_model_refresh with changed weights, caches computed with the
+    old weights are recomputed in full: the next call, an ordinary
+    incremental step, equals a GW_CACHE_FULL call on the same samples
+    bitwise and matches the oracle at the new weights."""
+    p0 = synth.deepclean_params(0)
+    params = torch.from_numpy(p0.copy()).to(DEV)
+    m = gs.DeepClean(params, LAYERS)
+    W, s = 4096, 256
+    st = Streams(m, W, 2, 70, W + 12 * s)
+    st.wit[1], st.strain[1] = st.wit[0], st.strain[0]
+    for _ in range(4):
+        st.update([0, 1], s)
+        st.forward([0], s)
+        st.forward([1], s, full=True)
+    rng = np.random.default_rng(9)
+    p1 = (p0 * np.exp(0.2 * rng.standard_normal(p0.shape))).astype(np.float32)
+    params.copy_(torch.from_numpy(p1))
+    m.refresh()
+    st.update([0, 1], s)
+    na, ca, _ = st.forward([0], s)
+    nb, cb, _ = st.forward([1], s, full=True)
+    assert np.array_equal(na, nb)
+    assert np.array_equal(ca, cb)
+    exp = ref.deepclean_forward(p1, st.window(0)[None], LAYERS)[0]
+    assert rel(na[0], exp) <= 2e-2
+
+
 def test_cached_rejects_bad_calls(model):
     W = 4096
     pool = gs.Pool(8 << 20, max_slots=2, max_items=4)

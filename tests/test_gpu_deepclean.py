@@ -226,6 +226,36 @@ def test_stream_restore_continues_bitwise(dc):
     assert e.value.code == gs.GW_EINVAL
 
 
+def test_refresh_rederives_every_inference_path():
+    """After the parameters change in place (as an optimizer step changes
+    them) and gw_model_refresh, every inference path (FP32, BF16 fused and
+    per layer, FP16 fused) computes with the new parameters: each matches
+    the oracle at the new parameters within its bound, while the change is
+    large enough that the old outputs are far outside it."""
+    layers = synth.deepclean_layers()
+    p0 = synth.deepclean_params(0)
+    params = torch.from_numpy(p0.copy()).to(DEV)
+    m = gs.DeepClean(params, layers)
+    wit, _ = synth.witness_stream(12, 2 * 4096)
+    x = np.ascontiguousarray(wit.reshape(21, 2, 4096).transpose(1, 0, 2))
+    old = run_dense(m, x, gs.BF16)
+    rng = np.random.default_rng(10)
+    p1 = (p0 * np.exp(0.2 * rng.standard_normal(p0.shape))).astype(np.float32)  # signs kept, variances > 0
+    params.copy_(torch.from_numpy(p1))
+    m.refresh()
+    torch.cuda.synchronize()
+    exp = ref.deepclean_forward(p1, x, layers)
+    assert rel(old, exp) > 5e-2
+    assert rel(run_dense(m, x, gs.FP32), exp) <= FP32_TOL
+    assert rel(run_dense(m, x, gs.BF16), exp) <= 2e-2
+    assert rel(run_dense(m, x, gs.FP16), exp) <= 2.5e-3
+    xt = torch.from_numpy(x).to(DEV)
+    noise = torch.empty((2, 4096), device=DEV)
+    m.forward(x=xt, noise=noise, precision=gs.BF16, flags=gs.LAYERWISE)
+    torch.cuda.synchronize()
+    assert rel(noise.cpu().numpy(), exp) <= 2e-2
+
+
 # --------------------------------------------------------------------------- streaming
 
 def test_streaming_8s_window_fp32(dc):
