@@ -33,6 +33,29 @@ def _fused_after_each_test(bb):
 MODES = [pytest.param(False, id="fused"), pytest.param(True, id="layerwise")]
 
 
+def test_bbhnet_refresh_rederives_every_path():
+    """After the parameters change in place and gw_model_refresh, the FP32
+    path and the BF16 fused and per-layer paths compute with the new
+    parameters (oracle at the new parameters), and the change is large
+    enough that the old logits are far outside the bounds."""
+    p0 = synth.bbhnet_params(0)
+    params = torch.from_numpy(p0.copy()).to(DEV)
+    m = gs.BBHnet(params, synth.bbhnet_stages())
+    x, _ = synth.bbh_windows(91, 32)
+    xt = torch.from_numpy(x).to(DEV)
+    old = m.forward(x=xt, precision=gs.BF16).cpu().numpy()
+    rng = np.random.default_rng(11)
+    p1 = (p0 * np.exp(0.2 * rng.standard_normal(p0.shape))).astype(np.float32)
+    params.copy_(torch.from_numpy(p1))
+    m.refresh()
+    exp = ref.bbhnet_forward(p1, x)
+    assert rel(old, exp) > 5e-2
+    assert rel(m.forward(x=xt).cpu().numpy(), exp) <= 1e-5
+    assert rel(m.forward(x=xt, precision=gs.BF16).cpu().numpy(), exp) <= 2e-2
+    m.set_layerwise(True)
+    assert rel(m.forward(x=xt, precision=gs.BF16).cpu().numpy(), exp) <= 2e-2
+
+
 @pytest.mark.parametrize("B", [64, 256, 1024])
 def test_bbhnet_fp32(bb, B):
     m, params = bb
