@@ -226,7 +226,7 @@ struct gw_pool {
     bool cache_valid = false;  // holds the window that ended cache_seen samples into the stream
     int cache_T = 0;           // its window start modulo W (ring heads)
     int64_t cache_seen = 0;
-    const void* cache_model = nullptr;  // the model and weight generation that computed it
+    uint64_t cache_model = 0;  // the id and weight generation of the model that computed it
     uint64_t cache_gen = 0;
   };
   // A closed slot's region whose last users may still be running: a later
@@ -562,8 +562,12 @@ constexpr int DENSE_ITEMS = 4096;  // item-table capacity for dense-input calls
 
 }  // namespace
 
+// process-wide model ids, never reused (a cache names the model that computed it)
+static std::atomic<uint64_t> g_next_model_id{1};
+
 struct gw_model {
   int kind = 0;
+  uint64_t id = g_next_model_id.fetch_add(1);
   uint64_t gen = 0;  // weight generation: counts gw_model_refresh calls
   std::vector<LayerD> layers;
   std::vector<StageD> stages;
@@ -1349,7 +1353,7 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     it.shadow = pool->shadow_elem(sl);
     it.in_head = sl.head;  // oldest sample of the current window
     const int64_t adv = sl.n_seen - sl.cache_seen;
-    if (!sl.cache_valid || sl.cache_model != m || sl.cache_gen != m->gen || (flags & GW_CACHE_FULL) || adv < 0 ||
+    if (!sl.cache_valid || sl.cache_model != m->id || sl.cache_gen != m->gen || (flags & GW_CACHE_FULL) || adv < 0 ||
         adv >= W || adv % 16) {
       it.shift = -1;
       it.T = 0;
@@ -1388,7 +1392,7 @@ extern "C" int deepclean_forward_cached(const gw_model* m, gw_pool* pool, const 
     sl.cache_valid = true;
     sl.cache_T = items[i].T;
     sl.cache_seen = sl.n_seen;
-    sl.cache_model = m;
+    sl.cache_model = m->id;
     sl.cache_gen = m->gen;
   }
   return GW_OK;

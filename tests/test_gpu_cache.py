@@ -3,8 +3,9 @@ caches (deepclean_forward_cached): an incrementally updated cache gives the
 bitwise same noise window and clean output as recomputing every position,
 over the zero-filled start, the ring's wrap and long runs; the outputs match
 the FP64 oracle within the BF16 bound; streams are independent of the rest
-of the batch; strides that are not multiples of 16, skipped calls and
-reattached caches fall back to a full recompute; bad calls are refused."""
+of the batch; strides that are not multiples of 16, skipped calls,
+reattached caches and caches computed by another model or before a refresh
+fall back to a full recompute; bad calls are refused."""
 import numpy as np
 import pytest
 import torch
@@ -160,6 +161,35 @@ def test_refresh_recomputes_caches():
     p1 = (p0 * np.exp(0.2 * rng.standard_normal(p0.shape))).astype(np.float32)
     params.copy_(torch.from_numpy(p1))
     m.refresh()
+    st.update([0, 1], s)
+    na, ca, _ = st.forward([0], s)
+    nb, cb, _ = st.forward([1], s, full=True)
+    assert np.array_equal(na, nb)
+    assert np.array_equal(ca, cb)
+    exp = ref.deepclean_forward(p1, st.window(0)[None], LAYERS)[0]
+    assert rel(na[0], exp) <= 2e-2
+
+
+def test_cache_from_another_model_recomputed():
+    """A cache computed by one model and then used by another (here one made
+    after the first was freed, with other weights) is recomputed in full:
+    the incremental call equals a GW_CACHE_FULL call bitwise and matches the
+    oracle at the second model's weights."""
+    p0 = synth.deepclean_params(0)
+    m0 = gs.DeepClean(torch.from_numpy(p0.copy()).to(DEV), LAYERS)
+    W, s = 4096, 256
+    st = Streams(m0, W, 2, 71, W + 12 * s)
+    st.wit[1], st.strain[1] = st.wit[0], st.strain[0]
+    for _ in range(4):
+        st.update([0, 1], s)
+        st.forward([0], s)
+        st.forward([1], s, full=True)
+    torch.cuda.synchronize()
+    st.m = None
+    del m0
+    rng = np.random.default_rng(10)
+    p1 = (p0 * np.exp(0.2 * rng.standard_normal(p0.shape))).astype(np.float32)
+    st.m = gs.DeepClean(torch.from_numpy(p1).to(DEV), LAYERS)
     st.update([0, 1], s)
     na, ca, _ = st.forward([0], s)
     nb, cb, _ = st.forward([1], s, full=True)
