@@ -108,6 +108,9 @@ def algorithmic(name, precision, layers, dc_s, bb_s):
         for (typ, ci, co, k, Li, Lo) in layer_shapes(layers, DC_W):
             macs += co * Lo * ci * k if typ == "conv" else ci * Li * co * k
         by = n * DC_C * DC_W * 2 + 2 * 4 * int(dc_s.sum())
+        # the step's launch also performs the snapshot update: the new
+        # samples read in FP32, written to the ring (FP32) and its BF16 shadow
+        by += DC_C * int(dc_s.sum()) * (4 + 4 + 2)
         return 2.0 * macs * n, float(by)
     if kind.startswith("bbh_conv"):
         st = int(tag[1:])
@@ -657,9 +660,12 @@ def main():
         bb.forward(pool=pool, slots=bb_sl, W=BB_W, logits=logits, precision=prec, ws=ws_bb, stream=st)
 
     def run_models(k, flags, delays=None, dc_prec=None, bb_stream=None):
-        pool.update(dc_sl, dc_str, staged[k], dc_off, stream=s_main)
-        dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=staged_strain[k], clean=clean,
-                   precision=prec if dc_prec is None else dc_prec, ws=ws_dc, flags=flags, delays=delays)
+        # the DeepClean streams' update and forward in one call (one launch on
+        # the fused BF16 path; the two calls otherwise); a request's new
+        # samples are also its clean stride
+        dc.update_forward(pool=pool, slots=dc_sl, strides=dc_s, samples=staged[k], offsets=dc_off, W=DC_W,
+                          strain=staged_strain[k], clean=clean, precision=prec if dc_prec is None else dc_prec,
+                          ws=ws_dc, flags=flags, delays=delays, stream=s_main)
         bbh_group(k, bb_stream)
 
     def step(k):
@@ -722,6 +728,8 @@ def main():
         if k >= 1:
             results_back(k - 1)
         s_main.wait_event(ev_in[b])
+        # the update and the forward as two calls: in this copy-bound loop the
+        # one-launch form (run_models) measured slower
         pool.update(dc_sl, dc_str, db, dc_off, stream=s_main)
         dc.forward(pool=pool, slots=dc_sl, W=DC_W, strides=dc_s, strain=db[per_step_floats:], clean=dev_clean[b],
                    precision=prec, ws=ws_dc, stream=s_main)

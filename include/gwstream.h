@@ -264,6 +264,28 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
                       void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * deepclean_update_forward (App. B.1, then the DeepClean forward of the main
+ * text): one request per stream, i.e. snapshot_update(pool, n, slots,
+ * strides, samples, offsets) followed by deepclean_forward(model, pool,
+ * slots, NULL, n, W, strides, delays, strain, noise, clean, precision, flags,
+ * ws, ws_bytes), with the same arguments, results and errors as those two
+ * calls: each stream's new samples are also its clean stride.  For BF16
+ * inference on the fused network (precision GW_BF16, flags 0, clean and
+ * strain given) it is one launch with one staged item table: each tile
+ * writes the new samples its input rows hold to the ring and its shadow
+ * (rounded as snapshot_update rounds them) before reading its rows, and no
+ * tile reads the ring positions those samples replace; outputs, rings and
+ * host state are bitwise those of the two calls.  Otherwise it makes the two
+ * calls.  On the one-launch path every argument is checked before any
+ * launch; on the other, an error from the forward's checks comes after the
+ * update has been enqueued.
+ */
+int deepclean_update_forward(const gw_model* model, gw_pool* pool, int32_t n, const int32_t* slots,
+                             const int32_t* strides, const float* samples, const int64_t* offsets, int32_t W,
+                             const int32_t* delays, const float* strain, float* noise, float* clean,
+                             int32_t precision, uint32_t flags, void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
  * Incremental DeepClean forward over per-stream activation caches.  The
  * stateful model hands each request's full window to the static model
  * (App. B.1), whose update step the paper names as the online bottleneck

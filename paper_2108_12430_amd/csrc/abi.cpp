@@ -1053,11 +1053,14 @@ extern "C" int deepclean_workspace(const gw_model* m, int32_t n, int32_t W, int3
   return GW_OK;
 }
 
-extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x,
-                                 int32_t n, int32_t W, const int32_t* strides, const int32_t* delays,
-                                 const float* strain, float* noise, float* clean, int32_t precision, uint32_t flags,
-                                 void* ws, size_t ws_bytes, void* hip_stream) {
-  const hipStream_t st = S(hip_stream);
+// deepclean_forward; with upd set (fused BF16 inference on pool input only),
+// the launch also performs the snapshot update whose new samples sit at
+// upd + upd_off[i]: the slots' host heads have already been advanced, so the
+// items carry the heads after the update
+static int dc_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x, int32_t n, int32_t W,
+                      const int32_t* strides, const int32_t* delays, const float* strain, float* noise, float* clean,
+                      int32_t precision, uint32_t flags, void* ws, size_t ws_bytes, hipStream_t st, const float* upd,
+                      const int64_t* upd_off) {
   if (!m) return fail(GW_EINVAL, "null model");
   if (m->kind != GW_MODEL_DEEPCLEAN) return fail(GW_ESTATE, "not a DeepClean model");
   if (n == 0) return GW_OK;
@@ -1126,6 +1129,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
         it.head = (s.head + a_band) % s.W;  // oldest sample of the band
         it.C = s.C;
         it.W = s.W;
+        if (upd) it.src = upd_off[i];
       }
       if (clean) {
         if (strides[i] < 1 || strides[i] > W) return fail(GW_EINVAL, "stride must be in [1, W]");
@@ -1165,6 +1169,7 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
     p.noise = noise;
     p.clean = clean;
     p.strain = strain;
+    p.upd = upd;
     const uint16_t* wpk[9];
     const float* sc[9];
     const float* sh[9];
@@ -1176,9 +1181,10 @@ extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t
       sh[l] = reinterpret_cast<const float*>(m->packed + m->layers[l].shift);
     }
     LAUNCH(f16 ? "dc_fused_f16" : "dc_fused_bf16", st,
-           gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, m->cu_budget, st, f16));
+           gw::launch_dc_fused_bf16(p, wpk, sc, sh, Wb, pool != nullptr, m->cu_budget, st, f16, upd != nullptr));
     return GW_OK;
   }
+  if (upd) return fail(GW_EINVAL, "the fused update runs on the fused BF16 inference path only");
   if (!(flags & GW_TRAIN)) {
     const float* in = x ? x + a_band : nullptr;
     for (int l = 0; l < L; ++l) {
@@ -1291,6 +1297,61 @@ int cache_layout(const gw_model* m, int W, gw::CacheLayerP& P, size_t* total) {
 }
 
 }  // namespace
+
+
+extern "C" int deepclean_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, const float* x,
+                                 int32_t n, int32_t W, const int32_t* strides, const int32_t* delays,
+                                 const float* strain, float* noise, float* clean, int32_t precision, uint32_t flags,
+                                 void* ws, size_t ws_bytes, void* hip_stream) {
+  return dc_forward(m, pool, slots, x, n, W, strides, delays, strain, noise, clean, precision, flags, ws, ws_bytes,
+                    S(hip_stream), nullptr, nullptr);
+}
+
+extern "C" int deepclean_update_forward(const gw_model* m, gw_pool* pool, int32_t n, const int32_t* slots,
+                                        const int32_t* strides, const float* samples, const int64_t* offsets,
+                                        int32_t W, const int32_t* delays, const float* strain, float* noise,
+                                        float* clean, int32_t precision, uint32_t flags, void* ws, size_t ws_bytes,
+                                        void* hip_stream) {
+  if (!m) return fail(GW_EINVAL, "null model");
+  if (!pool) return fail(GW_EINVAL, "null pool");
+  if (n == 0) return GW_OK;
+  if (n < 0 || n > pool->max_items) return fail(GW_EINVAL, "n out of range");
+  if (!slots || !strides || !samples || !offsets) return fail(GW_EINVAL, "null argument");
+  const bool one_launch =
+      m->kind == GW_MODEL_DEEPCLEAN && precision == GW_BF16 && m->fused && flags == 0 && clean && strain;
+  if (!one_launch) {
+    CHK(snapshot_update(pool, n, slots, strides, samples, offsets, hip_stream));
+    return deepclean_forward(m, pool, slots, nullptr, n, W, strides, delays, strain, noise, clean, precision, flags,
+                             ws, ws_bytes, hip_stream);
+  }
+  // the update's checks (the forward checks the rest before it launches)
+  std::vector<char> seen(pool->max_slots, 0);
+  for (int i = 0; i < n; ++i) {
+    CHK(pool->check_slot(slots[i]));
+    if (seen[slots[i]]) return fail(GW_EINVAL, "slot appears twice in one call");
+    seen[slots[i]] = 1;
+    if (strides[i] < 1 || strides[i] > pool->slots[slots[i]].W) return fail(GW_EINVAL, "stride must be in [1, W]");
+    if (offsets[i] < 0) return fail(GW_EINVAL, "negative sample offset");
+  }
+  // advance the host state as snapshot_update does; restored if the forward
+  // refuses the call
+  std::vector<std::pair<int, int64_t>> prev(n);
+  for (int i = 0; i < n; ++i) {
+    auto& sl = pool->slots[slots[i]];
+    prev[i] = {sl.head, sl.n_seen};
+    sl.head = (sl.head + strides[i]) % sl.W;
+    sl.n_seen += strides[i];
+  }
+  const int rc = dc_forward(m, pool, slots, nullptr, n, W, strides, delays, strain, noise, clean, precision, flags,
+                            ws, ws_bytes, S(hip_stream), samples, offsets);
+  if (rc != GW_OK)
+    for (int i = 0; i < n; ++i) {
+      auto& sl = pool->slots[slots[i]];
+      sl.head = prev[i].first;
+      sl.n_seen = prev[i].second;
+    }
+  return rc;
+}
 
 extern "C" int deepclean_cache_bytes(const gw_model* m, int32_t W, size_t* bytes) {
   if (!m || !bytes) return fail(GW_EINVAL, "null argument");

@@ -1500,10 +1500,67 @@ __device__ __forceinline__ void store_x(uint16_t* tile, const XRaw<IN>& R, int q
   }
 }
 
+// Fused snapshot update: the item carries the head after the update, and
+// its [C][s] new samples (FP32 at p.upd + src) belong at window positions
+// [W - s, W), ring positions h0, h0+1, ... (mod W), h0 = head - s.  Before a
+// tile stages its input rows [q0, q0 + XROWS), the block writes the new
+// samples among them (widened to whole groups of four) to the ring and its
+// BF16 shadow, exactly as the snapshot update writes them; after a barrier
+// the rows are read from the shadow as usual.  Every new position lies in
+// some tile's rows, so the launch writes them all; blocks whose rows overlap
+// write the same values.  No tile reads the positions the new samples
+// replace (they held the oldest samples, which left the window).
+// Returns false, writing nothing, when the rows hold no new sample
+// (block-uniform).
+__device__ __forceinline__ bool upd_stage(const ConvP& p, int b, int q0, int tid) {
+  const Item& it = p.items[b];
+  const int s = it.s, W = it.W, snew = W - s;
+  int lo = q0 > snew ? q0 : snew, hi = q0 + fused::XROWS < W ? q0 + fused::XROWS : W;
+  if (lo >= hi) return false;
+  // the arena is the pool's device memory; the launch owns these positions
+  float* ring = reinterpret_cast<float*>(const_cast<void*>(p.arena)) + it.ring;
+  uint16_t* sh = reinterpret_cast<uint16_t*>(const_cast<void*>(p.arena)) + it.shadow;
+  const float* src = p.upd + it.src;
+  int h0 = it.head - s;
+  if (h0 < 0) h0 += W;
+  const bool vec = ((s | h0 | W) & 3) == 0 && (it.src & 3) == 0 && (it.ring & 3) == 0 && (it.shadow & 3) == 0 &&
+                   (reinterpret_cast<uintptr_t>(p.upd) & 15) == 0;
+  if (vec) {
+    // groups of four samples of one channel; snew, W, s and h0 are multiples
+    // of 4, so a group stays inside [snew, W) and never straddles the wrap
+    lo = lo - ((lo - snew) & 3);
+    const int n4 = (hi - lo + 3) / 4, total = it.C * n4;
+    for (int g = tid; g < total; g += fused::NTHR) {
+      const int c = g / n4, q = lo + 4 * (g - c * n4) - snew;  // sample index within the new block
+      int ph = h0 + q;
+      if (ph >= W) ph -= W;
+      const float4 v = *reinterpret_cast<const float4*>(src + (int64_t)c * s + q);
+      *reinterpret_cast<float4*>(ring + (int64_t)c * W + ph) = v;
+      ushort4 h;
+      h.x = f2bf(v.x);
+      h.y = f2bf(v.y);
+      h.z = f2bf(v.z);
+      h.w = f2bf(v.w);
+      *reinterpret_cast<ushort4*>(sh + (int64_t)c * W + ph) = h;
+    }
+  } else {
+    const int n1 = hi - lo, total = it.C * n1;
+    for (int g = tid; g < total; g += fused::NTHR) {
+      const int c = g / n1, q = lo + (g - c * n1) - snew;
+      int ph = h0 + q;
+      if (ph >= W) ph -= W;
+      const float v = src[(int64_t)c * s + q];
+      ring[(int64_t)c * W + ph] = v;
+      sh[(int64_t)c * W + ph] = f2bf(v);
+    }
+  }
+  return true;
+}
+
 #ifndef GW_FUSED_WAVES_PER_SIMD
 #define GW_FUSED_WAVES_PER_SIMD 6
 #endif
-template <int IN, bool F16>
+template <int IN, bool F16, bool UPD = false>
 __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused(ConvP p, FusedP f, int ntile) {
   using namespace fused;
   __shared__ __attribute__((aligned(16))) uint16_t bufA[BUFA];
@@ -1519,6 +1576,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
   if (t0 >= t1) return;  // block-uniform
 
   XRaw<IN> raw;
+  if (UPD && upd_stage(p, t0 / tpw, (t0 % tpw) * T + LO[0], threadIdx.x)) __syncthreads();
   load_x<IN>(raw, p, t0 / tpw, (t0 % tpw) * T + LO[0], threadIdx.x);
   u32x4 wf[FMAX];  // this wave's weight fragments of the current layer
   fused_frags<0, 0, PF(0)>(wf, reinterpret_cast<const uint4*>(f.wpk[0]),
@@ -1572,6 +1630,7 @@ __global__ __launch_bounds__(fused::NTHR, GW_FUSED_WAVES_PER_SIMD) void dc_fused
       int tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
       const int nq = ((t + 1) % tpw) * T + LO[0];
+      if (UPD && upd_stage(p, (t + 1) / tpw, nq, tid)) __syncthreads();
       __builtin_amdgcn_s_setprio(2);  // ahead of the other block's epilogues
       load_x<IN>(raw, p, (t + 1) / tpw, nq, tid);
       store_x<IN, F16>(bufA, raw, nq, tid);
@@ -1646,9 +1705,10 @@ bool dc_fused_supported(const int* ci, const int* co, const int* type, const int
 // strain; W = window (or band) length, a multiple of 16.
 hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
                                 const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
-                                bool f16) {
+                                bool f16, bool upd) {
   using namespace fused;
   if (W < 16 || W % 16) return hipErrorInvalidValue;
+  if (upd && (!ring || f16 || !p.upd)) return hipErrorInvalidValue;
   FusedP f;
   for (int l = 0; l < 9; ++l) {
     f.wpk[l] = wpk[l];
@@ -1673,10 +1733,12 @@ hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, cons
   // one resident grid: (blocks per CU) x CUs, at most one block per tile
   // variants: (ring or dense input) x (BF16 or FP16); the FP16 variant reads
   // the ring's FP32 samples (its 16-bit shadow is BF16)
-  void (*kern[4])(ConvP, FusedP, int) = {dc_fused<IN_F32, false>, dc_fused<IN_RING, false>,
-                                         dc_fused<IN_F32, true>, dc_fused<IN_RING_F32, true>};
-  static int occ[4] = {0, 0, 0, 0}, cus = 0;
-  const int v = (ring ? 1 : 0) + (f16 ? 2 : 0);
+  // and the ring variant under a fused snapshot update
+  void (*kern[5])(ConvP, FusedP, int) = {dc_fused<IN_F32, false>, dc_fused<IN_RING, false>,
+                                         dc_fused<IN_F32, true>, dc_fused<IN_RING_F32, true>,
+                                         dc_fused<IN_RING, false, true>};
+  static int occ[5] = {0, 0, 0, 0, 0}, cus = 0;
+  const int v = upd ? 4 : (ring ? 1 : 0) + (f16 ? 2 : 0);
   if (!occ[v]) {
     int dev = 0, n = 0;
     hipError_t e = hipGetDevice(&dev);

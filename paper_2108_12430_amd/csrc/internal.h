@@ -72,6 +72,10 @@ struct ConvP {
   // Lin (a band at the end of longer windows); 0 means Lin.  Ring inputs wrap
   // at their item's W and read positions [head + q] for q in [0, Lin).
   int ldx;
+  // fused snapshot update (ring input, fused kernel only): item i's newest s
+  // samples, [C][s] FP32 at upd + items[i].src, are read from here rather
+  // than from the ring, and written to the ring and its shadow by the launch
+  const float* upd;
 };
 
 // ---- incremental DeepClean over per-stream activation caches ----
@@ -103,6 +107,15 @@ struct CacheItem {
   int32_t pad_;
 };
 static_assert(sizeof(CacheItem) == 48, "CacheItem layout");
+
+// float -> bfloat16, round to nearest even (NaN stays NaN): the ring's
+// shadow values, written by the snapshot update and by the fused update
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
 
 __host__ __device__ inline int cache_cdiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 // Dirty output positions of layer `layer` after the window advanced by
@@ -200,7 +213,7 @@ bool dc_fused_supported(const int* ci, const int* co, const int* type, const int
                         const int* pad, const int* op, const int* bn, int L);
 hipError_t launch_dc_fused_bf16(const ConvP& p, const uint16_t* const* wpk, const float* const* scale,
                                 const float* const* shift, int W, bool ring, int cu_budget, hipStream_t st,
-                                bool f16 = false);
+                                bool f16 = false, bool upd = false);
 size_t conv_bf16_packed_elems(int Ci, int Co, int k, bool transposed);
 // layers of the fused network whose weights the fused kernel takes in its own
 // fragment layout (stacked transposed layers, Toeplitz output conv)

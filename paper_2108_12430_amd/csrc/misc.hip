@@ -4,14 +4,6 @@
 
 namespace gw {
 
-// float -> bfloat16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
 // Snapshot update (the stateful model's request): item i writes its [C][s]
 // block of new samples at ring positions head, head+1, ... (mod W) of every
 // channel, both as the exact FP32 value and as its BF16 shadow.  After the

@@ -28,7 +28,7 @@ EXPORTS = [
     "gw_stream_info", "gw_stream_window", "gw_stream_load", "gw_pool_usage", "snapshot_update", "gw_model_packed_bytes",
     "gw_model_create", "gw_model_refresh", "gw_model_free", "gw_model_set_cu_budget", "gw_model_n_params",
     "gw_model_set_layerwise",
-    "deepclean_workspace", "deepclean_forward", "deepclean_overlap_average", "gw_decimate2",
+    "deepclean_workspace", "deepclean_forward", "deepclean_update_forward", "deepclean_overlap_average", "gw_decimate2",
     "deepclean_cache_bytes", "gw_stream_attach_cache", "deepclean_cache_bands", "deepclean_forward_cached",
     "deepclean_backward_scratch",
     "deepclean_backward",
@@ -76,6 +76,8 @@ def lib():
             "gw_model_n_params": ([i32, vp, i32, P(i64)], C.c_int),
             "deepclean_workspace": ([vp, i32, i32, i32, u32, P(sz)], C.c_int),
             "deepclean_forward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, i32, u32, vp, sz, vp], C.c_int),
+            "deepclean_update_forward": ([vp, vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, u32, vp, sz, vp],
+                                         C.c_int),
             "deepclean_overlap_average": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "gw_decimate2": ([i32, i32, i32, i32, vp, vp, vp, vp, vp], C.c_int),
             "deepclean_cache_bytes": ([vp, i32, P(sz)], C.c_int),
@@ -377,6 +379,26 @@ class DeepClean(_Model):
         check(lib().deepclean_forward(self.h, pool.h if pool is not None else None, psl, _ptr(x), n, W, pst, pdl,
                                       _ptr(strain), _ptr(noise), _ptr(clean), precision, flags, _ptr(ws),
                                       ws.numel(), _stream(stream)))
+        return ws
+
+    def update_forward(self, *, pool, slots, strides, samples, offsets, W, strain, clean, noise=None,
+                       precision=FP32, flags=0, ws=None, stream=None, delays=None):
+        """Enqueue deepclean_update_forward: pool.update(slots, strides,
+        samples, offsets) then forward(pool=pool, slots=slots, ...) with the
+        same strides, in one launch on the fused BF16 inference path."""
+        _f32(samples, "samples")
+        n = len(slots)
+        if ws is None:
+            ws = _buffer(self.workspace_bytes(n, W, precision, flags), self.device)
+        sl, psl = _host_i32(slots)
+        st, pst = _host_i32(strides)
+        of, pof = _host_i64(offsets)
+        dl = pdl = None
+        if delays is not None:
+            dl, pdl = _host_i32(delays)
+        check(lib().deepclean_update_forward(self.h, pool.h, n, psl, pst, _ptr(samples), pof, W, pdl, _ptr(strain),
+                                             _ptr(noise), _ptr(clean), precision, flags, _ptr(ws), ws.numel(),
+                                             _stream(stream)))
         return ws
 
     @staticmethod

@@ -29,7 +29,8 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # whose traffic bench.py reports; each entry is valid while its source's
 # hash is unchanged
 KERNELS = {
-    "dc_fused_bf16": ("void gw::dc_fused<2, false>(gw::ConvP, gw::FusedP, int)",
+    # the serving step's launch: the fused network with the snapshot update
+    "dc_fused_bf16": ("void gw::dc_fused<2, false, true>(gw::ConvP, gw::FusedP, int)",
                       "paper_2108_12430_amd/csrc/conv_bf16.hip"),
     "bbh_fused": ("gw::bbh_fused(gw::BbFusedP)", "paper_2108_12430_amd/csrc/bbh_fused.hip"),
     "snapshot": ("gw::snapshot_kernel(char*, gw::Item const*, float const*)",

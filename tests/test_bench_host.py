@@ -26,8 +26,10 @@ def test_more_than_one_gpu_is_refused():
 def test_fused_kernel_accounting():
     """Per launch: 2 x MACs of the nine layers for each of the 179 windows
     (per window, worked out layer by layer: 131,203,072 MACs at W = 32768),
-    and bytes = each window's 21 x 32768 BF16 input read once plus 4-byte
-    strain in and clean out for every new sample."""
+    and bytes = each window's 21 x 32768 BF16 input read once, 4-byte strain
+    in and clean out for every new sample, and the snapshot update the launch
+    performs: each new channel sample read in FP32 and written to the FP32
+    ring and its BF16 shadow."""
     dc_s, bb_s = bench.make_mix()
     macs = (8 * 16384 * 21 * 7 + 16 * 8192 * 8 * 7 + 32 * 4096 * 16 * 7 + 64 * 2048 * 32 * 7    # convs
             + 64 * 2048 * 32 * 7 + 32 * 4096 * 16 * 7 + 16 * 8192 * 8 * 7 + 8 * 16384 * 8 * 7  # transposed
@@ -35,7 +37,7 @@ def test_fused_kernel_accounting():
     assert macs == 131_203_072
     flops, by = bench.algorithmic("dc_fused_bf16", "bf16", synth.deepclean_layers(), dc_s, bb_s)
     assert flops == 2.0 * macs * bench.N_DC
-    assert by == bench.N_DC * 21 * 32768 * 2 + 8 * int(dc_s.sum())
+    assert by == bench.N_DC * 21 * 32768 * 2 + 8 * int(dc_s.sum()) + 21 * int(dc_s.sum()) * (4 + 4 + 2)
 
 
 def test_traffic_lookup_follows_the_kernel_source():

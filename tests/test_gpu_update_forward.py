@@ -1,0 +1,147 @@
+"""GPU tests of deepclean_update_forward (App. B.1 then the DeepClean
+forward): one call per request equals snapshot_update followed by
+deepclean_forward bitwise (clean output, noise window, FP32 ring, BF16
+shadow and host state), on the one-launch fused path (aligned and
+misaligned strides and offsets, strides of one sample up to the whole
+window, several tiles per block, delays) and on the two-call path (FP32);
+refused calls leave the streams untouched."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2108_12430_amd import gwstream as gs
+from paper_2108_12430_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LAYERS = synth.deepclean_layers()
+C = 21
+
+
+@pytest.fixture(scope="module")
+def model():
+    return gs.DeepClean(torch.from_numpy(synth.deepclean_params(0)).to(DEV), LAYERS)
+
+
+def make_pools(n, W):
+    pools, slots = [], []
+    for _ in range(2):
+        p = gs.Pool(n * (C * W * 6 + (1 << 16)) + (4 << 20), max_slots=n, max_items=n)
+        pools.append(p)
+        slots.append([p.open(C, W) for _ in range(n)])
+    return pools, slots
+
+
+def request(rng, strides, gap):
+    """Packed [C][s_i] blocks of new samples (gap floats after each block)
+    with their offsets, and the packed strain of the clean strides."""
+    blocks, offs, o = [], [], 0
+    for s in strides:
+        blk = rng.standard_normal(C * s).astype(np.float32)
+        blocks.append(np.concatenate([blk, np.zeros(gap, np.float32)]))
+        offs.append(o)
+        o += C * s + gap
+    samples = torch.from_numpy(np.concatenate(blocks)).to(DEV)
+    strain = torch.from_numpy(rng.standard_normal(int(sum(strides))).astype(np.float32)).to(DEV)
+    return samples, np.array(offs, np.int64), strain
+
+
+def run(model, W, steps, gap=0, precision=gs.BF16, delays=None, cu_budget=0, seed=0, noise=True):
+    n = len(steps[0])
+    pools, slots = make_pools(n, W)
+    rng = np.random.default_rng(seed)
+    model.set_cu_budget(cu_budget)
+    try:
+        for k, strides in enumerate(steps):
+            samples, offs, strain = request(rng, strides, gap)
+            outs = []
+            for side in range(2):
+                pool, sl = pools[side], slots[side]
+                nz = torch.full((n, W), 7.0, device=DEV) if noise else None
+                cl = torch.full((int(sum(strides)),), 7.0, device=DEV)
+                if side == 0:
+                    pool.update(sl, strides, samples, offs)
+                    model.forward(pool=pool, slots=sl, W=W, strides=strides, strain=strain, noise=nz, clean=cl,
+                                  precision=precision, delays=delays)
+                else:
+                    model.update_forward(pool=pool, slots=sl, strides=strides, samples=samples, offsets=offs, W=W,
+                                         strain=strain, noise=nz, clean=cl, precision=precision, delays=delays)
+                torch.cuda.synchronize()
+                outs.append((None if nz is None else nz.cpu().numpy(), cl.cpu().numpy()))
+            if noise:
+                assert np.array_equal(outs[0][0], outs[1][0]), k
+            assert np.array_equal(outs[0][1], outs[1][1]), k
+            for a, b in zip(slots[0], slots[1]):
+                assert pools[0].info(a) == pools[1].info(b), k
+                assert torch.equal(pools[0].window(a), pools[1].window(b)), k
+                assert torch.equal(pools[0].window(a, bf16=True), pools[1].window(b, bf16=True)), k
+    finally:
+        model.set_cu_budget(0)
+    return pools, slots
+
+
+def test_fused_update_forward_bitwise(model):
+    """21 x 32768 windows, strides 256/512/1024 (the serving mix), from the
+    zero-filled start."""
+    steps = [[256, 512, 1024, 1024, 256, 512]] * 5
+    run(model, 32768, steps)
+
+
+def test_fused_update_forward_many_tiles_per_block(model):
+    """A 4-CU budget: each block runs many tiles in turn, so the update's
+    writes happen in the tile loop's staging as well as before it."""
+    steps = [[256, 1024, 512]] * 3
+    run(model, 32768, steps, cu_budget=4)
+
+
+def test_fused_update_forward_ragged(model):
+    """Strides that are not multiples of 8 or 4 (the per-sample paths), one
+    sample, the whole window, misaligned sample offsets, and delays."""
+    W = 4096
+    steps = [[1, 13, 100, 4096, 768, 2048], [4096, 7, 1, 300, 5, 4092], [64, 4096, 3, 12, 2000, 1]]
+    run(model, W, steps, gap=1)
+    run(model, W, steps, gap=0, delays=[0, 0, 5, 0, 0, 0], seed=1)
+
+
+def test_two_call_path_bitwise(model):
+    """FP32 (not the fused kernel) takes the two calls."""
+    steps = [[256, 100, 1024]] * 2
+    run(model, 4096, steps, precision=gs.FP32)
+
+
+def test_fused_update_forward_matches_oracle(model):
+    """After three requests the fused call's noise window matches the FP64
+    oracle on the snapshot within the BF16 bound."""
+    W = 4096
+    pools, slots = run(model, W, [[256, 512]] * 3)
+    params = synth.deepclean_params(0)
+    nz = torch.empty((2, W), device=DEV)
+    model.forward(pool=pools[1], slots=slots[1], W=W, strides=[256, 512], strain=torch.zeros(768, device=DEV),
+                  noise=nz, clean=torch.empty(768, device=DEV), precision=gs.BF16)
+    torch.cuda.synchronize()
+    for i, sl in enumerate(slots[1]):
+        x = pools[1].window(sl).cpu().numpy()[None].astype(np.float64)
+        exp = ref.deepclean_forward(params, x, LAYERS)[0]
+        got = nz.cpu().numpy()[i]
+        assert np.max(np.abs(got - exp)) / np.max(np.abs(exp)) <= 2e-2
+
+
+def test_refused_call_leaves_streams(model):
+    """A forward-side refusal (window mismatch) restores the host state and
+    launches nothing."""
+    W = 4096
+    pool = gs.Pool(2 * (C * W * 6 + (1 << 16)) + (4 << 20), max_slots=2, max_items=2)
+    sl = [pool.open(C, W), pool.open(C, W)]
+    samples = torch.zeros(C * 512, device=DEV)
+    before = [pool.info(s) for s in sl]
+    with pytest.raises(gs.GwError):
+        model.update_forward(pool=pool, slots=sl, strides=[256, 256], samples=samples, offsets=[0, C * 256],
+                             W=2048, strain=torch.zeros(512, device=DEV), clean=torch.empty(512, device=DEV),
+                             precision=gs.BF16)
+    assert [pool.info(s) for s in sl] == before
+    with pytest.raises(gs.GwError):  # duplicate slot
+        model.update_forward(pool=pool, slots=[sl[0], sl[0]], strides=[256, 256], samples=samples,
+                             offsets=[0, C * 256], W=W, strain=torch.zeros(512, device=DEV),
+                             clean=torch.empty(512, device=DEV), precision=gs.BF16)
+    assert [pool.info(s) for s in sl] == before
