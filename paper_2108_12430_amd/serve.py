@@ -538,12 +538,14 @@ class HipExecutor:
                         ds[ps:ps + ns].copy_(pg.s[s0:s0 + ns], non_blocking=True)
                     px += nx
                     ps += ns
-            self.pool.update(slots, strides, dx, offsets, stream=st)
             out = b["d_o"][:n_out]
             if is_dc:
-                m.forward(pool=self.pool, slots=slots, W=W, strides=strides, strain=ds, clean=out,
-                          precision=self.precision, ws=ws, stream=st)
+                # the update and the forward in one call (one launch on the
+                # fused BF16 path)
+                m.update_forward(pool=self.pool, slots=slots, strides=strides, samples=dx, offsets=offsets, W=W,
+                                 strain=ds, clean=out, precision=self.precision, ws=ws, stream=st)
             else:
+                self.pool.update(slots, strides, dx, offsets, stream=st)
                 m.forward(pool=self.pool, slots=slots, W=W, logits=out, precision=self.precision, ws=ws,
                           stream=st)
             b["h_o"][:n_out].copy_(out, non_blocking=True)
