@@ -101,11 +101,13 @@ class Ensemble:
         cleaned, logits = self.cleaned_bufs[b], self.logit_bufs[b]
         if self.pipeline:
             main.wait_event(self.ev_post[b])  # the decimation that read this buffer is done
-        self.pool.update(self.slots_h1 + self.slots_l1, [s] * (2 * n), witness.reshape(-1), self.wit_off,
-                         stream=main)
+        # per detector: the witness update and the DeepClean forward in one
+        # call (one launch on the fused BF16 path)
+        wit = witness.reshape(-1)
         for d, slots in enumerate((self.slots_h1, self.slots_l1)):
-            self.dc[d].forward(pool=self.pool, slots=slots, W=self.W_dc, strides=[s] * n, strain=strain[d],
-                               clean=cleaned[d], precision=self.prec, ws=self.ws_dc, stream=main)
+            self.dc[d].update_forward(pool=self.pool, slots=slots, strides=[s] * n, samples=wit,
+                                      offsets=self.wit_off[d * n:(d + 1) * n], W=self.W_dc, strain=strain[d],
+                                      clean=cleaned[d], precision=self.prec, ws=self.ws_dc, stream=main)
         post = main
         if self.pipeline:
             self.ev_clean[b].record(main)
