@@ -911,8 +911,8 @@ def main():
             run_models(k, gs.CAUSAL, dls)
 
         def step_avg(k):
-            pool.update(dc_sl, dc_str, staged[k], dc_off, stream=s_main)
-            dc.forward(pool=pool, slots=dc_sl, W=DC_W, noise=noise_full, precision=prec, ws=ws_full)
+            dc.update_forward(pool=pool, slots=dc_sl, strides=dc_s, samples=staged[k], offsets=dc_off, W=DC_W,
+                              noise=noise_full, precision=prec, ws=ws_full, stream=s_main)
             dc.overlap_average(noise=noise_full, strides=dc_s, depth=depth, counts=[cnt[0]] * N_DC, state=state,
                                strain=staged_strain[k], clean=clean)
             cnt[0] += 1

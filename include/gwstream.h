@@ -270,8 +270,9 @@ int deepclean_forward(const gw_model* model, gw_pool* pool, const int32_t* slots
  * slots, NULL, n, W, strides, delays, strain, noise, clean, precision, flags,
  * ws, ws_bytes), with the same arguments, results and errors as those two
  * calls: each stream's new samples are also its clean stride.  For BF16
- * inference on the fused network (precision GW_BF16, flags 0, clean and
- * strain given) it is one launch with one staged item table: each tile
+ * inference on the fused network (precision GW_BF16, flags 0; noise, clean
+ * or both as for deepclean_forward) it is one launch with one staged item
+ * table: each tile
  * writes the new samples its input rows hold to the ring and its shadow
  * (rounded as snapshot_update rounds them) before reading its rows, and no
  * tile reads the ring positions those samples replace; outputs, rings and

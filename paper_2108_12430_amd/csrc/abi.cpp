@@ -1139,7 +1139,7 @@ static int dc_forward(const gw_model* m, gw_pool* pool, const int32_t* slots, co
         it.out = off;
         off += strides[i];
       } else {
-        it.s = 0;
+        it.s = upd ? strides[i] : 0;  // the update's new samples (no clean output to place)
       }
     }
   }
@@ -1317,8 +1317,7 @@ extern "C" int deepclean_update_forward(const gw_model* m, gw_pool* pool, int32_
   if (n == 0) return GW_OK;
   if (n < 0 || n > pool->max_items) return fail(GW_EINVAL, "n out of range");
   if (!slots || !strides || !samples || !offsets) return fail(GW_EINVAL, "null argument");
-  const bool one_launch =
-      m->kind == GW_MODEL_DEEPCLEAN && precision == GW_BF16 && m->fused && flags == 0 && clean && strain;
+  const bool one_launch = m->kind == GW_MODEL_DEEPCLEAN && precision == GW_BF16 && m->fused && flags == 0;
   if (!one_launch) {
     CHK(snapshot_update(pool, n, slots, strides, samples, offsets, hip_stream));
     return deepclean_forward(m, pool, slots, nullptr, n, W, strides, delays, strain, noise, clean, precision, flags,

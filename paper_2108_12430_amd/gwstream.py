@@ -381,7 +381,7 @@ class DeepClean(_Model):
                                       ws.numel(), _stream(stream)))
         return ws
 
-    def update_forward(self, *, pool, slots, strides, samples, offsets, W, strain, clean, noise=None,
+    def update_forward(self, *, pool, slots, strides, samples, offsets, W, strain=None, clean=None, noise=None,
                        precision=FP32, flags=0, ws=None, stream=None, delays=None):
         """Enqueue deepclean_update_forward: pool.update(slots, strides,
         samples, offsets) then forward(pool=pool, slots=slots, ...) with the

@@ -3,7 +3,8 @@ forward): one call per request equals snapshot_update followed by
 deepclean_forward bitwise (clean output, noise window, FP32 ring, BF16
 shadow and host state), on the one-launch fused path (aligned and
 misaligned strides and offsets, strides of one sample up to the whole
-window, several tiles per block, delays) and on the two-call path (FP32);
+window, several tiles per block, delays, noise windows only) and on the
+two-call path (FP32);
 refused calls leave the streams untouched."""
 import numpy as np
 import pytest
@@ -47,7 +48,7 @@ def request(rng, strides, gap):
     return samples, np.array(offs, np.int64), strain
 
 
-def run(model, W, steps, gap=0, precision=gs.BF16, delays=None, cu_budget=0, seed=0, noise=True):
+def run(model, W, steps, gap=0, precision=gs.BF16, delays=None, cu_budget=0, seed=0, noise=True, clean=True):
     n = len(steps[0])
     pools, slots = make_pools(n, W)
     rng = np.random.default_rng(seed)
@@ -59,19 +60,21 @@ def run(model, W, steps, gap=0, precision=gs.BF16, delays=None, cu_budget=0, see
             for side in range(2):
                 pool, sl = pools[side], slots[side]
                 nz = torch.full((n, W), 7.0, device=DEV) if noise else None
-                cl = torch.full((int(sum(strides)),), 7.0, device=DEV)
+                cl = torch.full((int(sum(strides)),), 7.0, device=DEV) if clean else None
+                sn = strain if clean else None
                 if side == 0:
                     pool.update(sl, strides, samples, offs)
-                    model.forward(pool=pool, slots=sl, W=W, strides=strides, strain=strain, noise=nz, clean=cl,
-                                  precision=precision, delays=delays)
+                    model.forward(pool=pool, slots=sl, W=W, strides=strides if clean else None, strain=sn,
+                                  noise=nz, clean=cl, precision=precision, delays=delays)
                 else:
                     model.update_forward(pool=pool, slots=sl, strides=strides, samples=samples, offsets=offs, W=W,
-                                         strain=strain, noise=nz, clean=cl, precision=precision, delays=delays)
+                                         strain=sn, noise=nz, clean=cl, precision=precision, delays=delays)
                 torch.cuda.synchronize()
-                outs.append((None if nz is None else nz.cpu().numpy(), cl.cpu().numpy()))
+                outs.append((None if nz is None else nz.cpu().numpy(), None if cl is None else cl.cpu().numpy()))
             if noise:
                 assert np.array_equal(outs[0][0], outs[1][0]), k
-            assert np.array_equal(outs[0][1], outs[1][1]), k
+            if clean:
+                assert np.array_equal(outs[0][1], outs[1][1]), k
             for a, b in zip(slots[0], slots[1]):
                 assert pools[0].info(a) == pools[1].info(b), k
                 assert torch.equal(pools[0].window(a), pools[1].window(b)), k
@@ -102,6 +105,13 @@ def test_fused_update_forward_ragged(model):
     steps = [[1, 13, 100, 4096, 768, 2048], [4096, 7, 1, 300, 5, 4092], [64, 4096, 3, 12, 2000, 1]]
     run(model, W, steps, gap=1)
     run(model, W, steps, gap=0, delays=[0, 0, 5, 0, 0, 0], seed=1)
+
+
+def test_fused_update_forward_noise_only(model):
+    """Noise windows only (no clean output), as for overlap averaging."""
+    steps = [[256, 100, 1024, 4096]] * 3
+    run(model, 4096, steps, clean=False)
+    run(model, 32768, [[512, 1024]] * 2, clean=False)
 
 
 def test_two_call_path_bitwise(model):
