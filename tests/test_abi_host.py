@@ -70,6 +70,8 @@ def test_null_and_range_arguments_rejected():
     assert L.snapshot_update(None, 1, None, None, None, None, None) == gs.GW_EINVAL
     assert L.deepclean_forward(None, None, None, None, 1, 4096, None, None, None, None, None, 0, 0, None, 0,
                                None) == gs.GW_EINVAL
+    assert L.deepclean_update_forward(None, None, 1, None, None, None, None, 4096, None, None, None, None, 1, 0,
+                                      None, 0, None) == gs.GW_EINVAL
     assert L.bbhnet_forward(None, None, None, None, 1, 2048, None, 0, None, 0, None) == gs.GW_EINVAL
     assert L.gw_model_set_cu_budget(None, 16) == gs.GW_EINVAL
     b = C.c_size_t()
